@@ -1,0 +1,203 @@
+"""Throughput benchmark of the Kob-Andersen MD hot path on one MI355X.
+
+Default workload: N = 1,048,576 Kob-Andersen particles (80:20) at density
+1.2 and T = 0.45, dt = 0.005, mixed precision with 64-bit fixed-point force
+accumulation.  Set-up (not timed): simple-cubic lattice with B/A swaps,
+Maxwell-Boltzmann velocities, stochastic-bath equilibration, neighbour-list
+autotuning, warm-up steps.  Timed: K velocity-Verlet NVE steps replayed from a
+captured HIP graph (forces, integration and every neighbour-list rebuild
+included).  One JSON line on stdout.
+
+Also measured (reported in extra keys): the plain FP64 GPU path on the same
+workload, the energy drift of the timed window, the force kernel's mean
+duration from HIP events (roofline) and the FP64 CPU oracle on a bounded
+sample (cpu_baseline).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PAIR = 19          # FP32 FLOPs per in-cutoff pair force (FMA = 2)
+FP32_VECTOR_PEAK = 157.3    # TFLOP/s, MI355X published dense vector peak
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=200)
+    p.add_argument("--workload", default="large", choices=["small", "medium", "large"])
+    p.add_argument("--precision", default="mixed_fixed", choices=["fp64", "mixed", "mixed_fixed"])
+    p.add_argument("--equil", type=int, default=6000, help="stochastic-bath steps before timing")
+    p.add_argument("--no-autotune", action="store_true")
+    p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison run")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--profile-steps", type=int, default=200)
+    return p.parse_args()
+
+
+def make_system(wl, precision, md):
+    rep = wl.replicas[0]
+    init = "rsa" if rep.n <= 300000 else "lattice"
+    return md.System([(rep.n, rep.n_a, rep.box, rep.temperature, rep.seed)], precision=precision,
+                     dt=wl.dt, skin=0.3, init=init, auto_sync=False), init
+
+
+def equilibrate(s, md, nsteps):
+    if nsteps <= 0:
+        return
+    # melt/thermalise with frequent redraws first, then the paper's ~50-step bath
+    s.step_nvt(min(500, nsteps), md.NVT_STOCHASTIC, n_reassign=10)
+    if nsteps > 500:
+        s.step_nvt(nsteps - 500, md.NVT_STOCHASTIC, n_reassign=50)
+    w = s.status()
+    if w:
+        raise RuntimeError(f"device error word 0x{w:x} during equilibration")
+
+
+def timed_graph(s, md, torch, steps):
+    md.md_graph_capture(s.ctx, steps, 0)
+    md.md_graph_launch(s.ctx)  # warm replay (also checks the graph)
+    s.stream.synchronize()
+    e0 = s.observables()[0, 4]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    md.md_graph_launch(s.ctx)
+    s.stream.synchronize()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    e1 = s.observables()[0, 4]
+    return t1 - t0, e0, e1
+
+
+def cpu_baseline(wl, seconds):
+    import oracle as O
+    from paper_2001_07089_amd import workload as W
+    rep = wl.replicas[0]
+    x, y, z = W.lattice_config(rep.n, rep.box, rep.seed, 0.1)
+    vx, vy, vz = W.gaussian_velocities(rep.n, math.sqrt(rep.temperature), rep.seed + 1)
+    st = O.State(x, y, z, vx, vy, vz, rep.n_a, rep.box)
+    t0 = time.perf_counter()
+    st.compute_forces("cell")
+    tf = time.perf_counter() - t0
+    nsteps = max(1, min(200, int(seconds / max(tf, 1e-6))))
+    t0 = time.perf_counter()
+    O.run(st, wl.dt, nsteps, method="cell")
+    el = time.perf_counter() - t0
+    return {"value": rep.n * nsteps / el, "unit": "atom-steps/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{nsteps} velocity-Verlet NVE steps of the same N={rep.n} system "
+                      f"(cell-list oracle, FP64, OpenMP), {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for {a.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2001_07089_amd import md
+    from paper_2001_07089_amd import workload as W
+
+    wl = {"small": W.ka_small, "medium": W.ka_medium, "large": W.ka_large}[a.workload]()
+    rep = wl.replicas[0]
+    n = rep.n
+    log(f"workload {wl.name}: N={n} L={rep.box:.6f} T={rep.temperature} precision={a.precision}")
+
+    t0 = time.perf_counter()
+    s, init = make_system(wl, a.precision, md)
+    log(f"init ({init}) {time.perf_counter() - t0:.1f} s")
+    equilibrate(s, md, a.equil)
+    log(f"equilibrated {a.equil} steps, {time.perf_counter() - t0:.1f} s")
+    tune = None
+    if not a.no_autotune:
+        tune = md.md_autotune(s.ctx, 60)
+        log(f"autotune: {tune}")
+    s.step_nve(a.warmup)
+    s.stream.synchronize()
+    el, e0, e1 = timed_graph(s, md, torch, a.steps)
+    value = n * a.steps / el
+    drift = abs(e1 - e0) / abs(e0) * (1e4 / a.steps)
+    log(f"timed {a.steps} steps: {el * 1e3:.1f} ms -> {value:.4e} atom-steps/s, "
+        f"E/N {e0 / n:.6f} -> {e1 / n:.6f}, drift per 1e4 steps {drift:.2e}")
+    prof = md.md_profile(s.ctx, a.profile_steps)
+    st = md.md_stats(s.ctx)
+    w = s.status()
+    log(f"profile: {prof}")
+    log(f"stats: {st}  err=0x{w:x}")
+    pairs = prof["pairs"]
+    flops = pairs * FLOP_PER_PAIR
+    achieved = flops / (prof["force_ms"] * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
+            "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
+            "kernel": f"force_{a.precision}", "kernel_ms": prof["force_ms"],
+            "ordered_pairs_per_launch": pairs}
+    skin = st["skin"]
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+
+    fp64 = None
+    if not a.no_fp64 and a.precision != "fp64":
+        s2, _ = make_system(wl, "fp64", md)
+        equilibrate(s2, md, a.equil)
+        md.md_set_list_params(s2.ctx, skin, int(st["cell_div"]))
+        s2.step_nve(a.warmup)
+        k2 = max(100, a.steps // 2)
+        el2, f0, f1 = timed_graph(s2, md, torch, k2)
+        p2 = md.md_profile(s2.ctx, min(100, a.profile_steps))
+        fp64 = {"value": n * k2 / el2, "steps": k2, "ms_per_step": el2 * 1e3 / k2,
+                "drift_per_1e4": abs(f1 - f0) / abs(f0) * (1e4 / k2), "force_ms": p2["force_ms"]}
+        log(f"fp64 GPU: {fp64}")
+        s2.close()
+        del s2
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not a.no_cpu:
+        cpu = cpu_baseline(wl, a.cpu_seconds)
+        log(f"cpu oracle: {cpu}")
+
+    out = {
+        "metric": "atom-steps/s, KA LJ N=1M + batched replicas, mixed vs FP64, ≤1e-4 drift",
+        "value": value,
+        "unit": "atom-steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": el * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "mixed": "f32/f64", "mixed_fixed": "f32/f64/i64"}[a.precision],
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_atoms": n, "precision": a.precision, "dt": wl.dt,
+                   "skin": skin, "cell_div": int(st["cell_div"]), "init": init, "equil_steps": a.equil,
+                   "hip_graph": True, "parallelism": "single-gpu"},
+        "drift_per_1e4_steps": drift,
+        "energy_per_atom": [e0 / n, e1 / n],
+        "rebuilds_per_step": prof["rebuilds"] / prof["steps"],
+        "roofline": roof,
+        "fp64_gpu": fp64,
+        "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
+        "cpu_baseline": cpu,
+        "autotune": tune,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

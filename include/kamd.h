@@ -1,0 +1,270 @@
+/*
+ * kamd.h -- C ABI of the MI355X (gfx950) Kob-Andersen binary Lennard-Jones
+ * molecular-dynamics library.
+ *
+ * Method: "Introduction to molecular dynamics simulations", K. Vollmayr-Lee,
+ * arXiv:2001.07089.  The library advances one or many independent systems
+ * ("replicas") of the Kob-Andersen 80:20 mixture (Sec. II.B) in cubic periodic
+ * boxes (Sec. II.C) with velocity Verlet (Sec. II.D), the stochastic bath
+ * (Sec. II.E.1, Sec. III.G) or Nose-Hoover via Fox-Andersen (Appendix B), and
+ * measures the radial distribution function (Sec. VI.A) and the mean-square
+ * displacement (Sec. VI.B) on the device.
+ *
+ * General rules
+ *   - Every function returns an int: KAMD_OK (0) or a negative error code.
+ *     Functions never throw, exit or print; md_last_error() gives a message.
+ *   - Device pointers are plain HIP device addresses (for example the
+ *     data_ptr() of a torch CUDA tensor); host pointers are ordinary memory.
+ *     Which is which is stated per argument.
+ *   - Arrays described as "caller order" are indexed by the caller's particle
+ *     index: replica r occupies [offset_r, offset_r + n_r), its A particles
+ *     first (the paper stores the A block before the B block, Sec. III.A).
+ *     Particle type is implied by that position; masses are 1 (Sec. II.B).
+ *   - All work is enqueued on the caller's HIP stream given to md_init and
+ *     returns without waiting, except where a function is marked "syncs".
+ *   - The context owns its internal device memory (allocated in md_init,
+ *     released in md_destroy).  Caller-owned buffers are only borrowed.
+ *   - One context must not be used from two host threads at once.
+ */
+#ifndef KAMD_H
+#define KAMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+enum {
+    KAMD_OK = 0,
+    KAMD_EINVAL = -1,  /* invalid argument                                  */
+    KAMD_ENOMEM = -2,  /* device memory or the admission budget is exceeded */
+    KAMD_EHIP = -3,    /* a HIP runtime call failed (no device, ...)        */
+    KAMD_EDEVICE = -4, /* the sticky device error word is set (md_status)   */
+    KAMD_EBOX = -5,    /* box too small: largest cutoff + skin >= L/2       */
+    KAMD_ESTATE = -6   /* call not valid in the current state               */
+};
+
+/* Arithmetic of the pair-force kernels. */
+enum {
+    KAMD_PREC_FP64 = 0,        /* binary64 throughout                                  */
+    KAMD_PREC_MIXED = 1,       /* FP32 pair distances, LJ terms and pair forces from an
+                                  exact fixed-point separation; FP32 per-particle partial
+                                  sums converted to FP64; FP64 integration + reductions  */
+    KAMD_PREC_MIXED_FIXED = 2  /* as MIXED, but every pair force is rounded to a 64-bit
+                                  fixed-point integer (2^-26 units) and summed exactly:
+                                  the force is independent of summation order            */
+};
+
+/* md_forces flags. */
+enum { KAMD_F_FORCE = 1, KAMD_F_ENERGY = 2, KAMD_F_VIRIAL = 4 };
+
+/* Thermostats for md_step_nvt. */
+enum { KAMD_NVT_STOCHASTIC = 0, KAMD_NVT_NOSE_HOOVER = 1 };
+
+/* Initial positions for md_init. */
+enum {
+    KAMD_INIT_GIVEN = 0,   /* positions and velocities are read from the caller arrays   */
+    KAMD_INIT_RSA = 1,     /* random sequential addition with a minimum pair distance,
+                              then Maxwell-Boltzmann velocities                           */
+    KAMD_INIT_LATTICE = 2  /* simple cubic lattice with B/A swaps (Sec. III.A), then
+                              Maxwell-Boltzmann velocities                                */
+};
+
+/* Bits of the sticky device error word (md_status). */
+enum {
+    KAMD_DEV_NONFINITE = 1u,     /* a position, velocity or force became inf/nan       */
+    KAMD_DEV_LIST_OVERFLOW = 2u, /* a neighbour list exceeded its capacity            */
+    KAMD_DEV_FORCE_RANGE = 4u    /* a pair force left the fixed-point range            */
+};
+
+/* Pair model: epsilon and sigma per pair type in the order AA, AB, BB, and the
+ * cutoff factor (r_c = rc_factor * sigma).  Kob-Andersen values, Sec. II.B:
+ * eps = {1, 1.5, 0.5}, sigma = {1, 0.8, 0.88}, rc_factor = 2.5. */
+typedef struct {
+    double eps[3];
+    double sigma[3];
+    double rc_factor;
+} kamd_model;
+
+/* One replica: n particles of which the first n_a are type A, in a cubic box
+ * of edge `box`, at bath temperature `temperature` (k_B = 1), with its own
+ * random seed.  `offset` is its first index in the caller-order arrays. */
+typedef struct {
+    int64_t offset;
+    int32_t n;
+    int32_t n_a;
+    double box;
+    double temperature;
+    uint64_t seed;
+} kamd_replica;
+
+/* Caller-order state arrays (device pointers, FP64, length n_total = sum of
+ * n).  img holds the periodic image counters as three blocks of n_total int32
+ * (x, y, z): the unwrapped position is x + img*L (Sec. VI.B.1).  Any pointer
+ * may be NULL when the caller does not want that array exported. */
+typedef struct {
+    double *x, *y, *z;
+    double *vx, *vy, *vz;
+    double *ax, *ay, *az;
+    int32_t *img;
+} kamd_state;
+
+/* Run configuration. */
+typedef struct {
+    kamd_model model;
+    int32_t precision;      /* KAMD_PREC_*                                          */
+    double dt;              /* time step (LJ units)                                 */
+    double skin;            /* neighbour-list skin; < 0 selects 0.3                 */
+    int32_t init_mode;      /* KAMD_INIT_*                                          */
+    double min_dist;        /* minimum pair distance of KAMD_INIT_RSA (e.g. 0.8)    */
+    int32_t cell_div;       /* list cells per list radius: 1 or 2 (0 = 1)           */
+    double list_capacity;   /* neighbour-list rows as a multiple of the expected
+                               count (0 = 1.6)                                      */
+    int32_t auto_sync;      /* 1: export state to the caller arrays after every call */
+} kamd_config;
+
+/* Device bytes md_init would allocate for this configuration (host call, no
+ * device needed).  Used for admission to HBM. */
+int md_workspace_size(const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
+                      size_t *bytes);
+
+/* Admission by memory footprint: walks the replicas in order and marks each
+ * admitted[r] = 1 while the running footprint stays within budget_bytes,
+ * else 0.  Host call.  *n_admitted receives the count. */
+int md_admit(const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
+             size_t budget_bytes, int32_t *admitted, int32_t *n_admitted);
+
+typedef struct kamd_ctx kamd_ctx;
+
+/* Create a context on the current HIP device and stream `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  reps[] describes n_rep replicas
+ * (host memory, copied).  st gives the caller-order device arrays: with
+ * KAMD_INIT_GIVEN, x/y/z (in [0, L) per replica) and vx/vy/vz are read; with
+ * the other init modes they are generated (RSA/lattice on the host from the
+ * replica seed, velocities by the Maxwell-Boltzmann flow chart of Sec. II.E.1
+ * at the replica temperature) and written to st.  Initial forces are computed
+ * (the "Initialization" box of the flow chart in Sec. II.D) and written to
+ * st->ax.. when given.  Errors: KAMD_EINVAL (bad sizes, n_a outside [0, n],
+ * mass-free model), KAMD_EBOX (largest cutoff >= L/2), KAMD_ENOMEM,
+ * KAMD_EHIP.  On error *out is NULL. */
+int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
+            const kamd_state *st, void *hip_stream);
+
+/* Rebuild the cell lists and neighbour lists of every replica now: bin by
+ * cell, stable counting sort of the internal particle order, pair list of all
+ * partners within r_c(ab) + skin (the neighbour list of Sec. III.E; LAMMPS'
+ * "bin" build, Sec. IV).  Rebuilds also happen automatically inside the step
+ * functions whenever a particle has moved more than skin/2 since the last
+ * build. */
+int md_build_cells(kamd_ctx *ctx);
+
+/* Forces at the current positions, Eq. (KAFix) with the truncation of
+ * Eq. (VshiftedKALJ) (strict r < r_c(ab)).  The accelerations (m = 1) are
+ * kept for the next step and exported to st->ax.. when auto_sync is on.
+ * With KAMD_F_ENERGY and/or KAMD_F_VIRIAL, obs_dev (device, FP64 [n_rep][2])
+ * receives per replica the shifted potential energy sum_{i<j} V_ij^cutoff and
+ * the virial W = sum_{i<j} r_ij . F_ij; obs_dev may be NULL otherwise. */
+int md_forces(kamd_ctx *ctx, uint32_t flags, double *obs_dev);
+
+/* nsteps velocity-Verlet steps in the order of Sec. II.D / Sec. III.E:
+ * r += v dt + a dt^2/2, wrap, v += a dt/2, a = F(r), v += a dt/2
+ * (Eqs. (velVerletPos),(velVerletVel)). */
+int md_step_nve(kamd_ctx *ctx, int32_t nsteps);
+
+/* nsteps steps at constant N, V, T.
+ * mode KAMD_NVT_STOCHASTIC: the NVE step, then every n_reassign steps (counted
+ * from the context's step counter) all velocities are redrawn with the
+ * Maxwell-Boltzmann flow chart of Sec. II.E.1 (Sec. III.G).
+ * mode KAMD_NVT_NOSE_HOOVER: Eqs. (Noseupdate_ri)-(Noseupdate_xiapprox) and
+ * (ridotKVLRoman) of Appendix B with X = 3N and bath mass Q = 3 N T tau^2;
+ * the friction xi and ln s persist in the context.  tau > 0 is required for
+ * this mode; n_reassign > 0 for the stochastic mode. */
+int md_step_nvt(kamd_ctx *ctx, int32_t nsteps, int32_t mode, int32_t n_reassign, double tau);
+
+/* Add one radial-distribution measurement (Sec. VI.A.1) of the current
+ * configuration to hist_dev (device, uint64 [n_rep][3][n_bins], pair rows AA,
+ * AB, BB; accumulated, the caller zeroes it): for every unique pair the
+ * minimum-image distance r, bin = int(r / dr), counted when bin < n_bins;
+ * AA and BB rows add 2 per pair, AB adds 1.  Requires n_bins*dr <= L/2 for
+ * every replica (else KAMD_EINVAL).  Normalisation to g_ab(r) (Eqs. (gAA),
+ * (gAB)) is left to the caller. */
+int md_rdf(kamd_ctx *ctx, double dr, int32_t n_bins, uint64_t *hist_dev);
+
+/* Mean-square displacement (Eqs. (msdwithi),(msdtw)) with unwrapped
+ * coordinates (Sec. VI.B.1).  op 0 (SET_ORIGIN): store the current unwrapped
+ * positions as origin `slot` (0 <= slot < 16).  op 1 (MEASURE): out_dev
+ * (device, FP64 [n_rep][2]) receives per replica {msd_A, msd_B} against origin
+ * `slot`. */
+int md_msd(kamd_ctx *ctx, int32_t op, int32_t slot, double *out_dev);
+
+/* Current observables per replica into host_out (host, FP64 [n_rep][6]):
+ * {KE, PE, W, T, E_tot, P} with KE = sum v^2/2, PE the shifted potential,
+ * T = 2 KE / (3N) (Eq. (equip3N)), E_tot = KE + PE (Eq. (EsysNpart)) and
+ * pressure P = N T / V + W / (3V).  Syncs. */
+int md_observables(kamd_ctx *ctx, double *host_out);
+
+/* Nose-Hoover state per replica into host_out (host, FP64 [n_rep][2]):
+ * {xi, ln s}.  Syncs. */
+int md_thermostat_state(kamd_ctx *ctx, double *host_out);
+
+/* Write the internal state to the caller-order arrays given to md_init. */
+int md_sync(kamd_ctx *ctx);
+
+/* Re-read positions, velocities and image counters from the caller-order
+ * arrays (after the caller changed them), recompute forces. */
+int md_import(kamd_ctx *ctx);
+
+/* Record nsteps steps of md_step_nve (ensemble 0) or md_step_nvt (ensemble 1,
+ * with mode/n_reassign/tau) into a HIP graph held by the context, replacing
+ * any earlier one.  Rebuild decisions stay on the device.  Nothing is
+ * executed.  md_graph_launch(ctx) replays it on the context stream. */
+int md_graph_capture(kamd_ctx *ctx, int32_t nsteps, int32_t ensemble, int32_t mode,
+                     int32_t n_reassign, double tau);
+int md_graph_launch(kamd_ctx *ctx);
+
+/* Neighbour-list tuning: time probe_steps NVE steps for each candidate skin
+ * (0.2 .. min(0.5, L/2 - r_c,max)) and each cell division (1, 2) on a copy
+ * of the current state, keep the fastest, restore the state.  Results in
+ * host_out (host, FP64 [3]): {skin, cell_div, ms_per_step}.  Syncs. */
+int md_autotune(kamd_ctx *ctx, int32_t probe_steps, double *host_out);
+
+/* Change skin and cell division (forces a rebuild at the next step). */
+int md_set_list_params(kamd_ctx *ctx, double skin, int32_t cell_div);
+
+/* Statistics: host_out (host, FP64 [8]) = {steps, rebuilds, n_total,
+ * list_rows, mean_list_len, max_list_len, skin, cell_div}.  Syncs. */
+int md_stats(kamd_ctx *ctx, double *host_out);
+
+/* Checkpoint: the full dynamical state (positions, velocities, forces, image
+ * counters, thermostat variables, step counter) in caller order, as a host
+ * blob.  With blob == NULL, *bytes receives the size.  Syncs. */
+int md_get_state(kamd_ctx *ctx, void *blob, size_t *bytes);
+int md_set_state(kamd_ctx *ctx, const void *blob, size_t bytes);
+
+/* Measurement: nsteps NVE steps run eagerly on the context stream with HIP
+ * events around every force-kernel launch and every streaming (drift/kick)
+ * launch.  host_out (host, FP64 [8]) = {mean force-kernel ms, mean streaming
+ * ms per step, total ms, list rebuilds during the run, ordered pairs inside
+ * the cutoff per force launch (from a closing energy pass), steps, mean
+ * rebuild-chain ms per step, 0}.  Syncs. */
+int md_profile(kamd_ctx *ctx, int32_t nsteps, double *host_out);
+
+/* Synchronise the stream and report the sticky device error word (KAMD_DEV_*
+ * bits) in *word; returns KAMD_EDEVICE when it is non-zero.  Syncs. */
+int md_status(kamd_ctx *ctx, uint32_t *word);
+
+/* Message of the last error on this context (or of the last failed md_init
+ * when ctx is NULL).  Never NULL. */
+const char *md_last_error(const kamd_ctx *ctx);
+
+/* Release the context and its device memory (waits for the stream). */
+int md_destroy(kamd_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KAMD_H */

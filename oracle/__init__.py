@@ -89,8 +89,14 @@ def lib():
         L.ora_msd.restype = None
         L.ora_log_schedule.argtypes = [C.c_int, C.c_double, C.c_int, _I32, C.c_int]
         L.ora_log_schedule.restype = C.c_int
+        L.ora_num_threads.argtypes = []
+        L.ora_num_threads.restype = C.c_int
         _LIB = L
     return _LIB
+
+
+def num_threads() -> int:
+    return int(lib().ora_num_threads())
 
 
 def _c(a, dtype=np.float64):

@@ -25,6 +25,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 /* Model table: epsilon and sigma per pair type, cutoff factor (Sec. II.B,
  * Eq. (VKALJ) and the truncation of Eq. (VshiftedKALJ)). */
@@ -561,4 +564,14 @@ int ora_log_schedule(int nmd, double t0, int kmax, int32_t *out, int maxout)
         }
     }
     return cnt;
+}
+
+/* Threads the OpenMP loops of this file will use. */
+int ora_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

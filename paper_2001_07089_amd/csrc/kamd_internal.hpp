@@ -1,0 +1,179 @@
+// kamd_internal.hpp -- internal layout shared by the host runtime and the HIP
+// kernels of the Kob-Andersen MD library (not part of the public ABI).
+//
+// Internal particle order ("slots").  Each replica r contributes two
+// segments, its A particles then its B particles, each padded to a multiple of
+// the 64-lane wavefront.  Every wavefront therefore covers particles of one
+// replica and one type, so the box, the pair parameters of its rows and its
+// reductions are wavefront-uniform (the type-split loops of the paper's
+// acceleration routine, Sec. III.D, mapped onto waves).  Within a segment the
+// particles are kept sorted by list cell (stable counting sort), which gives
+// coalesced streaming and cache-local neighbour gathers.  Padding slots have
+// id = -1, zero state, no list entries and are never anybody's neighbour.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kamd.h"
+
+namespace kamd {
+
+constexpr int WAVE = 64;
+constexpr int BLOCK = 256;               // threads per block for slot kernels
+constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
+constexpr int LIST_ROW_ALIGN = 4;        // neighbour rows are padded to this multiple
+
+// Neighbour-list layout.  The list of wavefront w is a block of rows * 64
+// ints; entry k of lane l sits at (k / 4) * 256 + l * 4 + k % 4 inside it:
+// each lane's entries come in 16-byte chunks of four, and chunk g of all 64
+// lanes is 1 KB contiguous.  A lane therefore writes its list 16 contiguous
+// bytes at a time, and a wavefront reads four rows with one coalesced int4
+// load per lane.
+__host__ __device__ inline size_t list_index(int w, int rows, int k, int lane)
+{
+    return (size_t)w * rows * 64 + (size_t)(k >> 2) * 256 + (size_t)lane * 4 + (k & 3);
+}
+constexpr double FIX_SCALE = 67108864.0; // 2^26 fixed-point units per force unit
+constexpr double FIX_MAGIC = 6755399441055744.0;  // 1.5 * 2^52
+
+struct SegInfo {
+    int32_t rep;    // replica
+    int32_t type;   // 0 = A, 1 = B
+    int32_t slot0;  // first slot
+    int32_t n;      // particles
+    int32_t npad;   // slots (multiple of WAVE)
+    int32_t cell0;  // first cell of this segment's list grid
+    int32_t ncell;  // nc^3
+    int32_t pad_;
+};
+
+struct RepInfo {
+    double L, invL;
+    double T;
+    uint64_t seed;
+    int64_t caller_off;    // first caller-order index
+    int32_t n, na;
+    int32_t seg[2];        // segment indices (A, B)
+    int32_t wave0, wave1;  // waves [wave0, wave1) of both segments
+    int32_t nc;            // list cells per box edge
+    int32_t rdf_nc;        // cells per edge of the last RDF grid
+    double skin;
+    double disp_thr2;      // rebuild when max |dr|^2 exceeds this (real units)
+    // pair constants in the u32 fixed-point length unit h = L / 2^32
+    float rc2_fx[3];       // r_c(ab)^2 / h^2
+    float rl2_fx[3];       // (r_c(ab) + skin)^2 / h^2, slightly enlarged
+    float sig2_fx[3];      // sigma(ab)^2 / h^2
+    float pad0_;
+    double c48_h[3];       // 48 eps(ab) / h: converts the fixed-unit sum to a force
+    double fix_k[3];       // 48 eps(ab) / h * FIX_SCALE
+    double fx_to_len;      // h
+    int32_t rdf_cell0;     // first RDF cell of this replica
+    int32_t rdf_ncell;
+};
+
+// Pair model in real units (binary64), AA/AB/BB.
+struct Model {
+    double eps[3];
+    double sig2[3];
+    double rc2[3];
+    double vshift[3];
+};
+
+// Per-replica device-side mutable scalars.
+struct RepDyn {
+    double xi, lns, xia;  // Nose-Hoover friction, ln s, xi_approx for the running step
+    double K2;            // sum v^2 at the start of the running step
+    double c_kick;        // half-kick factor of the running step
+    double pad[3];
+};
+
+// All device pointers, passed by value to kernels.
+struct Dev {
+    // slot-order state
+    double *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az;
+    int32_t *img;         // [3][npad_total]
+    int32_t *id;          // caller global index or -1
+    uint4 *mirror;        // u32 fixed-point positions (x, y, z, 0)
+    uint4 *mbuild;        // mirror at the last list build
+    // permutation scratch (same layout)
+    double *sx, *sy, *sz, *svx, *svy, *svz, *sax, *say, *saz;
+    int32_t *simg, *sid;
+    uint4 *smirror;
+    // layout tables
+    const SegInfo *seg;
+    const RepInfo *rep;
+    const int32_t *wave_seg;
+    const int32_t *cell_seg;
+    // cells and lists
+    int32_t *cell_of, *rank, *cell_count, *cell_start, *cell_end, *order;
+    int32_t *rb_force;    // per replica: rebuild at the next check regardless
+    uint32_t *maxdisp;    // per replica: max |r - r_build|^2 (float bits) since the last check
+    int32_t *nbr;         // per wave: rows x 64 entries, see list_index
+    int2 *kmax;           // per wave: rows of the A part, rows of the B part
+    int32_t *nlen;        // per slot: true list length (stats)
+    // reductions
+    double *wred;         // per wave [4]
+    double *rsum;         // per replica [4]
+    double *obs;          // per replica [8]: KE2, PE, W, -, ...
+    RepDyn *dyn;
+    uint32_t *err;
+    int32_t *counters;    // [0] = rebuilds, [1] = device step counter
+    // RDF scratch
+    int32_t *rdf_cell_of, *rdf_rank, *rdf_count, *rdf_start;
+    double4 *rdf_pos;
+    const int32_t *rdf_block_rep;
+    const int32_t *rdf_block_start;
+    // MSD origins [16][3][n_total] in caller order
+    double *origin;
+    // sizes
+    int32_t npad_total;
+    int32_t n_total;
+    int32_t nwaves;
+    int32_t nrep;
+    int32_t ncells;
+    int32_t rows;         // neighbour-list row capacity
+};
+
+
+// ---------------------------------------------------------------- launchers
+// Each returns hipGetLastError() after its launch(es).
+hipError_t launch_rb_assign(const Dev &d, hipStream_t s);
+hipError_t launch_rb_scan(const Dev &d, int nseg, hipStream_t s);
+hipError_t launch_rb_scatter(const Dev &d, hipStream_t s);
+hipError_t launch_rb_sortgather(const Dev &d, hipStream_t s);
+hipError_t launch_rb_list(const Dev &d, int cell_div, hipStream_t s);
+
+// The force kernel also closes the step's rebuild check (resets maxdisp and
+// rb_force) and, with step_inc, advances the device step counter.
+hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, bool step_inc, hipStream_t s);
+
+hipError_t launch_drift(const Dev &d, double dt, hipStream_t s);
+hipError_t launch_drift_nh(const Dev &d, double dt, hipStream_t s);
+hipError_t launch_kick_nve(const Dev &d, double dt, bool want_ke, hipStream_t s);
+hipError_t launch_kick_nh(const Dev &d, hipStream_t s);
+hipError_t launch_kick_drift(const Dev &d, double dt, bool want_ke, hipStream_t s);
+hipError_t launch_rep_reduce(const Dev &d, int mask, hipStream_t s);
+hipError_t launch_nh_begin(const Dev &d, double dt, const double *Q, hipStream_t s);
+hipError_t launch_nh_end(const Dev &d, double dt, const double *Q, hipStream_t s);
+hipError_t launch_set_k2(const Dev &d, hipStream_t s);
+hipError_t launch_mb_draw(const Dev &d, uint32_t tag, hipStream_t s);
+hipError_t launch_mb_draw_dev(const Dev &d, hipStream_t s);
+hipError_t launch_mb_center(const Dev &d, hipStream_t s);
+hipError_t launch_mb_scale(const Dev &d, hipStream_t s);
+hipError_t launch_ke_partial(const Dev &d, hipStream_t s);
+
+hipError_t launch_import(const Dev &d, const double *const *arr, const int32_t *img, hipStream_t s);
+hipError_t launch_export(const Dev &d, double *const *arr, int32_t *img, hipStream_t s);
+hipError_t launch_mirror(const Dev &d, hipStream_t s);
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
+hipError_t launch_store_obs(const Dev &d, double *out, hipStream_t s);
+hipError_t launch_store_pe_w(const Dev &d, double *out, hipStream_t s);
+
+hipError_t launch_rdf_prepare(const Dev &d, hipStream_t s);
+hipError_t launch_rdf(const Dev &d, double dr, int nbins, int nblocks, uint64_t *hist, hipStream_t s);
+hipError_t launch_msd_set(const Dev &d, int slot, hipStream_t s);
+hipError_t launch_msd_measure(const Dev &d, int slot, hipStream_t s);
+hipError_t launch_msd_finish(const Dev &d, double *out, hipStream_t s);
+
+}  // namespace kamd

@@ -1,0 +1,221 @@
+// kernels_analysis.hip -- on-device radial distribution histogram and
+// mean-square displacement.
+//
+// This translation unit is compiled without floating-point contraction so that
+// the pair distance of the histogram is evaluated exactly as the definition
+// reads: separations in binary64, minimum image by one +-L correction when
+// the separation exceeds L/2 (the branch form of Sec. III.D),
+// r^2 = (dx dx + dy dy) + dz dz, r = sqrt(r^2) (IEEE, correctly rounded),
+// bin = int(r / dr) by a true division (Sec. VI.A.1).  The counts are then
+// identical to those of any other IEEE evaluation of the same definition.
+#include "common_dev.hpp"
+
+namespace kamd {
+
+// RDF grid: per replica rdf_nc^3 cells of edge L/rdf_nc >= n_bins*dr, both
+// particle types together.  Counting sort into rdf_pos (replica-relative
+// positions, w = type + 2*cell).
+__global__ __launch_bounds__(BLOCK) void k_rdf_assign(Dev d)
+{
+    const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    if (w >= d.nwaves) return;
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    const int s = w * WAVE + lane_id();
+    if (s - S.slot0 >= S.n) return;
+    const RepInfo &R = d.rep[S.rep];
+    const int nc = R.rdf_nc;
+    const uint4 m = d.mirror[s];
+    const int c = R.rdf_cell0 + (fix_cell(m.z, nc) * nc + fix_cell(m.y, nc)) * nc + fix_cell(m.x, nc);
+    d.rdf_cell_of[s] = c;
+    d.rdf_rank[s] = atomicAdd(&d.rdf_count[c], 1);
+}
+
+// Exclusive scan per replica; rdf_start holds indices into rdf_pos
+// (the replica's range begins at its caller offset).
+__global__ __launch_bounds__(1024) void k_rdf_scan(Dev d)
+{
+    __shared__ int part[1024];
+    const RepInfo &R = d.rep[blockIdx.x];
+    const int n = R.rdf_ncell;
+    const int chunk = (n + 1023) / 1024;
+    const int b = threadIdx.x * chunk;
+    const int e = min(n, b + chunk);
+    int sum = 0;
+    for (int c = b; c < e; ++c) sum += d.rdf_count[R.rdf_cell0 + c];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int run = (int)R.caller_off + part[threadIdx.x] - sum;
+    for (int c = b; c < e; ++c) {
+        d.rdf_start[R.rdf_cell0 + c] = run;
+        run += d.rdf_count[R.rdf_cell0 + c];
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rdf_scatter(Dev d)
+{
+    const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    if (w >= d.nwaves) return;
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    const int s = w * WAVE + lane_id();
+    if (s - S.slot0 >= S.n) return;
+    const RepInfo &R = d.rep[S.rep];
+    const int c = d.rdf_cell_of[s];
+    const int t = d.rdf_start[c] + d.rdf_rank[s];
+    d.rdf_pos[t] = make_double4(d.x[s], d.y[s], d.z[s], (double)(S.type + 2 * (c - R.rdf_cell0)));
+}
+
+__device__ inline double min_image_branch(double dd, double L, double half)
+{
+    if (dd > half) dd -= L;
+    else if (dd < -half) dd += L;
+    return dd;
+}
+
+// One block of BLOCK particles of one replica (block table from the host).
+// Each particle visits the distinct stencil cells of its own and counts the
+// partners with a larger index, so every unordered pair is counted once.
+// Block-local u32 histograms in LDS, flushed to the uint64 result.
+__global__ __launch_bounds__(BLOCK) void k_rdf_hist(Dev d, double dr, int nbins, uint64_t *hist)
+{
+    extern __shared__ uint32_t lh[];  // [3][nbins]
+    const int rep = d.rdf_block_rep[blockIdx.x];
+    const int i0 = d.rdf_block_start[blockIdx.x];
+    const RepInfo &R = d.rep[rep];
+    for (int b = threadIdx.x; b < 3 * nbins; b += BLOCK) lh[b] = 0u;
+    __syncthreads();
+    const int iend = (int)R.caller_off + R.n;
+    const int i = i0 + (int)threadIdx.x;
+    if (i < iend) {
+        const double4 pi = d.rdf_pos[i];
+        const int wi = (int)pi.w;
+        const int ti = wi & 1;
+        const int cl = wi >> 1;
+        const int nc = R.rdf_nc;
+        const int cx = cl % nc, cy = (cl / nc) % nc, cz = cl / (nc * nc);
+        const int noff = min(nc, 3);
+        const double L = R.L, half = 0.5 * R.L;
+        for (int oz = -1; oz < -1 + noff; ++oz) {
+            const int qz = (cz + oz + nc) % nc;
+            for (int oy = -1; oy < -1 + noff; ++oy) {
+                const int qy = (cy + oy + nc) % nc;
+                for (int ox = -1; ox < -1 + noff; ++ox) {
+                    const int qx = (cx + ox + nc) % nc;
+                    const int c = R.rdf_cell0 + (qz * nc + qy) * nc + qx;
+                    const int st = d.rdf_start[c];
+                    const int en = st + d.rdf_count[c];
+                    for (int j = max(st, i + 1); j < en; ++j) {
+                        const double4 pj = d.rdf_pos[j];
+                        const double dx = min_image_branch(pi.x - pj.x, L, half);
+                        const double dy = min_image_branch(pi.y - pj.y, L, half);
+                        const double dz = min_image_branch(pi.z - pj.z, L, half);
+                        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+                        const int bin = (int)(r / dr);
+                        if (bin < nbins) {
+                            const int p = ti + (((int)pj.w) & 1);
+                            atomicAdd(&lh[p * nbins + bin], p == 1 ? 1u : 2u);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    uint64_t *h = hist + (size_t)rep * 3 * nbins;
+    for (int b = threadIdx.x; b < 3 * nbins; b += BLOCK)
+        if (lh[b]) atomicAdd((unsigned long long *)&h[b], (unsigned long long)lh[b]);
+}
+
+// MSD: origin[slot][k][id] = unwrapped coordinate k (x + img L, Sec. VI.B.1).
+__global__ __launch_bounds__(BLOCK) void k_msd_set(Dev d, int slot)
+{
+    const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    if (w >= d.nwaves) return;
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    const int s = w * WAVE + lane_id();
+    if (s - S.slot0 >= S.n) return;
+    const double L = d.rep[S.rep].L;
+    const int np = d.npad_total;
+    const int g = d.id[s];
+    double *o = d.origin + (size_t)slot * 3 * d.n_total;
+    o[g] = d.x[s] + (double)d.img[s] * L;
+    o[d.n_total + g] = d.y[s] + (double)d.img[np + s] * L;
+    o[2 * d.n_total + g] = d.z[s] + (double)d.img[2 * np + s] * L;
+}
+
+// Per-wave sum of |r_u - r_u(origin)|^2, stored in component `type` of the
+// wave partials (a wave holds one type).
+__global__ __launch_bounds__(BLOCK) void k_msd_measure(Dev d, int slot)
+{
+    const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    if (w >= d.nwaves) return;
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    const int s = w * WAVE + lane_id();
+    double d2 = 0.0;
+    if (s - S.slot0 < S.n) {
+        const double L = d.rep[S.rep].L;
+        const int np = d.npad_total;
+        const int g = d.id[s];
+        const double *o = d.origin + (size_t)slot * 3 * d.n_total;
+        const double ux = d.x[s] + (double)d.img[s] * L - o[g];
+        const double uy = d.y[s] + (double)d.img[np + s] * L - o[d.n_total + g];
+        const double uz = d.z[s] + (double)d.img[2 * np + s] * L - o[2 * d.n_total + g];
+        d2 = ux * ux + uy * uy + uz * uz;
+    }
+    d2 = wave_sum(d2);
+    if (lane_id() == 0) {
+        d.wred[4 * w + 0] = S.type == 0 ? d2 : 0.0;
+        d.wred[4 * w + 1] = S.type == 1 ? d2 : 0.0;
+    }
+}
+
+__global__ void k_msd_finish(Dev d, double *out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= d.nrep) return;
+    const RepInfo &R = d.rep[r];
+    out[2 * r + 0] = R.na > 0 ? d.rsum[4 * r + 0] / (double)R.na : 0.0;
+    out[2 * r + 1] = R.n - R.na > 0 ? d.rsum[4 * r + 1] / (double)(R.n - R.na) : 0.0;
+}
+
+static inline int nblk(const Dev &d) { return (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
+
+hipError_t launch_rdf_prepare(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rdf_assign, dim3(nblk(d)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_rdf_scan, dim3(d.nrep), dim3(1024), 0, s, d);
+    hipLaunchKernelGGL(k_rdf_scatter, dim3(nblk(d)), dim3(BLOCK), 0, s, d);
+    return hipGetLastError();
+}
+
+hipError_t launch_rdf(const Dev &d, double dr, int nbins, int nblocks, uint64_t *hist, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rdf_hist, dim3(nblocks), dim3(BLOCK), sizeof(uint32_t) * 3 * nbins, s, d, dr,
+                       nbins, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_msd_set(const Dev &d, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_msd_set, dim3(nblk(d)), dim3(BLOCK), 0, s, d, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_msd_measure(const Dev &d, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_msd_measure, dim3(nblk(d)), dim3(BLOCK), 0, s, d, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_msd_finish(const Dev &d, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_msd_finish, dim3((d.nrep + 63) / 64), dim3(64), 0, s, d, out);
+    return hipGetLastError();
+}
+
+}  // namespace kamd

@@ -1,0 +1,352 @@
+// kernels_build.hip -- cell binning, stable counting sort of the internal
+// particle order and the neighbour lists.
+//
+// The paper evaluates forces by a double loop over all pairs and names the
+// neighbour list as the optimisation it leaves out (end of Sec. III.E); its
+// LAMMPS runs use a binned list with a skin and a rebuild check every step
+// (Sec. IV, "neighbor 0.3 bin" with "check yes").  Here each replica has a
+// cubic grid of nc^3 cells of edge L/nc >= (largest cutoff + skin)/cell_div,
+// and each particle keeps the list of all partners within r_c(ab) + skin,
+// rebuilt when some particle of the replica has moved more than skin/2 since
+// the last build (so no pair can enter the cutoff unseen).
+//
+// A rebuild runs as five kernels.  Each one evaluates the replica's rebuild
+// flag itself (rebuild_flag) and returns at once when it is clear, so the
+// decision stays on the device and the step loop can be captured in a HIP
+// graph:
+//   rb_assign     per particle: cell index, rank inside the cell (one atomic
+//                 per run of lanes that share a cell)
+//   rb_scan       per segment: exclusive scan of the counters -> cell ranges
+//   rb_scatter    per particle: provisional destination slot
+//   rb_sortgather per cell: order the cell by previous slot (a stable sort:
+//                 the result does not depend on atomic timing), gather the
+//                 particles' state into the scratch arrays, clear the counter
+//   rb_list       per particle: copy its state back, record the build
+//                 position, write its neighbour list
+#include "common_dev.hpp"
+
+namespace kamd {
+
+__global__ __launch_bounds__(BLOCK) void k_rb_assign(Dev d)
+{
+    const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    if (w >= d.nwaves) return;
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    if (!rebuild_flag(d, S.rep)) return;
+    const int lane = lane_id();
+    const int s = w * WAVE + lane;
+    const bool real = (s - S.slot0) < S.n;
+    const int nc = d.rep[S.rep].nc;
+    int c = -1 - lane;  // distinct dummy for padding lanes
+    if (real) {
+        const uint4 m = d.mirror[s];
+        c = S.cell0 + (fix_cell(m.z, nc) * nc + fix_cell(m.y, nc)) * nc + fix_cell(m.x, nc);
+        d.cell_of[s] = c;
+    }
+    // Runs of consecutive lanes with the same cell (the slots are still in the
+    // order of the previous build, so most neighbours share a cell): the first
+    // lane of a run reserves the whole run with one atomic.
+    const int prev = __shfl_up(c, 1, 64);
+    const bool head = (lane == 0) || (prev != c);
+    const uint64_t heads = __ballot(head);
+    const uint64_t below = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    const int first = 63 - __clzll((long long)(heads & below));  // head of my run
+    const uint64_t above = heads & ~below;
+    const int next = above ? __ffsll((long long)above) - 1 : 64;  // head of the next run
+    int base = 0;
+    if (head && real) base = atomicAdd(&d.cell_count[c], next - lane);
+    base = __shfl(base, first, 64);
+    if (real) d.rank[s] = base + (lane - first);
+    (void)next;
+}
+
+// Exclusive scan of one segment's cell counters into absolute slot ranges
+// [cell_start, cell_end).  One block of 1024 threads per segment; each pass
+// scans 8192 counters (8 consecutive per thread, wavefront shuffles, then the
+// 16 wavefront totals).
+__global__ __launch_bounds__(1024) void k_rb_scan(Dev d)
+{
+    __shared__ int wtot[16];
+    __shared__ int carry_s;
+    const SegInfo &S = d.seg[blockIdx.x];
+    if (!rebuild_flag(d, S.rep)) return;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    if (t == 0) {
+        carry_s = 0;
+        if (S.type == 0) atomicAdd(&d.counters[0], 1);
+    }
+    __syncthreads();
+    const int n = S.ncell;
+    const int32_t *cnt = d.cell_count + S.cell0;
+    for (int base = 0; base < n; base += 8192) {
+        int v[8];
+        int sum = 0;
+        const int i0 = base + 8 * t;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v[k] = (i0 + k < n) ? cnt[i0 + k] : 0;
+            sum += v[k];
+        }
+        int inc = sum;  // inclusive scan over the wavefront
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int u = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += u;
+        }
+        if (lane == 63) wtot[wv] = inc;
+        __syncthreads();
+        if (t == 0) {
+            int run = 0;
+            for (int k = 0; k < 16; ++k) { const int x = wtot[k]; wtot[k] = run; run += x; }
+        }
+        __syncthreads();
+        int run = S.slot0 + carry_s + wtot[wv] + inc - sum;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (i0 + k < n) {
+                d.cell_start[S.cell0 + i0 + k] = run;
+                run += v[k];
+                d.cell_end[S.cell0 + i0 + k] = run;
+            }
+        }
+        __syncthreads();
+        if (t == 1023) carry_s = run - S.slot0;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rb_scatter(Dev d)
+{
+    const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    if (w >= d.nwaves) return;
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    if (!rebuild_flag(d, S.rep)) return;
+    const int s = w * WAVE + lane_id();
+    if (s - S.slot0 >= S.n) return;
+    d.order[d.cell_start[d.cell_of[s]] + d.rank[s]] = s;
+}
+
+__device__ inline void gather_one(const Dev &d, int v, int t)
+{
+    const int np = d.npad_total;
+    d.sx[t] = d.x[v];
+    d.sy[t] = d.y[v];
+    d.sz[t] = d.z[v];
+    d.svx[t] = d.vx[v];
+    d.svy[t] = d.vy[v];
+    d.svz[t] = d.vz[v];
+    d.sax[t] = d.ax[v];
+    d.say[t] = d.ay[v];
+    d.saz[t] = d.az[v];
+    d.simg[t] = d.img[v];
+    d.simg[np + t] = d.img[np + v];
+    d.simg[2 * np + t] = d.img[2 * np + v];
+    d.sid[t] = d.id[v];
+    d.smirror[t] = d.mirror[v];
+}
+
+// One wavefront per cell.  The destination of each member is its rank by
+// previous slot, which makes the counting sort stable.  Cells of up to 64
+// members rank in registers; larger ones (only tiny boxes with 1-2 cells per
+// edge) fall back to a loop over memory.
+__global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
+{
+    const int c = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    if (c >= d.ncells) return;
+    const SegInfo &S = d.seg[d.cell_seg[c]];
+    if (!rebuild_flag(d, S.rep)) return;
+    const int st = d.cell_start[c];
+    const int m = d.cell_end[c] - st;
+    const int lane = lane_id();
+    if (m <= WAVE) {
+        const int v = lane < m ? d.order[st + lane] : 0x7fffffff;
+        int rank = 0;
+        for (int e2 = 0; e2 < m; ++e2) rank += (__shfl(v, e2, 64) < v) ? 1 : 0;
+        if (lane < m) gather_one(d, v, st + rank);
+    } else {
+        for (int e = lane; e < m; e += WAVE) {
+            const int v = d.order[st + e];
+            int rank = 0;
+            for (int e2 = 0; e2 < m; ++e2) rank += (d.order[st + e2] < v) ? 1 : 0;
+            gather_one(d, v, st + rank);
+        }
+    }
+    if (lane == 0) d.cell_count[c] = 0;  // ready for the next rebuild
+}
+
+// Neighbour lists.  One thread per particle.  Entries [0, kA) of a list hold
+// the particle's A partners, entries [kA, kA + kB) its B partners, where kA,
+// kB are the wavefront maxima rounded up to LIST_ROW_ALIGN; unused entries
+// hold the particle's own slot, which the force kernels skip (zero
+// separation).  Storage follows list_index: a particle appends 16 contiguous
+// bytes at a time, so cache lines fill completely before they leave the L2.
+//
+// The stencil is walked row by row: the cells of one stencil row differ only
+// in x and are consecutive in the cell-sorted slot order, so a row is one
+// contiguous slot range (two when it wraps around the box), scanned with
+// eight gathers in flight.  Rows, and the end cells of a row, that lie
+// farther than the list radius from the particle are skipped (in FP64, with a
+// margin, when the grid has at least 2*reach+1 cells per edge).
+//
+// Candidate test in u32 fixed-point units: the integer difference of two
+// coordinates is the minimum-image separation (the box maps onto the full
+// 2^32 range), converted to float; rl2_fx is enlarged by a few parts in 10^6
+// so that the list is a superset of the exact one.
+constexpr int LIST_UNROLL = 8;
+
+__device__ inline double gap(int o, int c, double cw, double u)
+{
+    return o > 0 ? (c + o) * cw - u : (o < 0 ? u - (c + o + 1) * cw : 0.0);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
+{
+    const int w = wave_id_remapped();  // each XCD walks a contiguous slot range
+    if (w >= d.nwaves) return;
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    const int rep = S.rep;
+    if (!rebuild_flag(d, rep)) return;
+    const RepInfo &R = d.rep[rep];
+    const int lane = lane_id();
+    const int s = w * WAVE + lane;
+    const bool real = (s - S.slot0) < S.n;
+    const int np = d.npad_total;
+    uint4 mi = make_uint4(0, 0, 0, 0);
+    if (real) {
+        d.x[s] = d.sx[s];
+        d.y[s] = d.sy[s];
+        d.z[s] = d.sz[s];
+        d.vx[s] = d.svx[s];
+        d.vy[s] = d.svy[s];
+        d.vz[s] = d.svz[s];
+        d.ax[s] = d.sax[s];
+        d.ay[s] = d.say[s];
+        d.az[s] = d.saz[s];
+        d.img[s] = d.simg[s];
+        d.img[np + s] = d.simg[np + s];
+        d.img[2 * np + s] = d.simg[2 * np + s];
+        d.id[s] = d.sid[s];
+        mi = d.smirror[s];
+        d.mirror[s] = mi;
+        d.mbuild[s] = mi;
+    }
+    const int nc = R.nc;
+    const int noff = min(nc, 2 * reach + 1);
+    const bool prune = nc >= 2 * reach + 1;
+    const int cx = fix_cell(mi.x, nc), cy = fix_cell(mi.y, nc), cz = fix_cell(mi.z, nc);
+    const double cw = 4294967296.0 / (double)nc;  // cell edge in fixed units
+    const double ux = (double)mi.x, uy = (double)mi.y, uz = (double)mi.z;
+    int32_t *col = d.nbr + list_index(w, d.rows, 0, lane);
+    const int rows = d.rows;
+    int row = 0;
+    int total = 0;
+    int kpart[2];
+    for (int tj = 0; tj < 2; ++tj) {
+        const SegInfo &SJ = d.seg[R.seg[tj]];
+        const float rl2 = R.rl2_fx[S.type + tj];
+        const double rp = sqrt((double)rl2) + 4096.0;  // pruning radius with margin
+        const double rp2 = rp * rp;
+        int cnt = 0;
+        auto scan = [&](int st, int en) {
+            for (int j = st; j < en; j += LIST_UNROLL) {
+                uint4 mj[LIST_UNROLL];
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) mj[u] = d.smirror[min(j + u, en - 1)];
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) {
+                    const float dx = (float)(int)(mi.x - mj[u].x);
+                    const float dy = (float)(int)(mi.y - mj[u].y);
+                    const float dz = (float)(int)(mi.z - mj[u].z);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    if (j + u < en && r2 < rl2 && r2 > 0.0f) {
+                        const int k = row + cnt;
+                        if (k < rows) col[(k >> 2) * 256 + (k & 3)] = j + u;
+                        ++cnt;
+                    }
+                }
+            }
+        };
+        if (real && SJ.n > 0) {
+            for (int oz = -reach; oz < -reach + noff; ++oz) {
+                const double gz = prune ? fmax(gap(oz, cz, cw, uz), 0.0) : 0.0;
+                const int qz = (cz + oz + nc) % nc;
+                for (int oy = -reach; oy < -reach + noff; ++oy) {
+                    const double gy = prune ? fmax(gap(oy, cy, cw, uy), 0.0) : 0.0;
+                    const double g2 = gy * gy + gz * gz;
+                    if (g2 > rp2) continue;
+                    const int qy = (cy + oy + nc) % nc;
+                    const int rowc = SJ.cell0 + (qz * nc + qy) * nc;  // cell (0, qy, qz)
+                    if (!prune) {  // every cell of the row is in the stencil
+                        scan(d.cell_start[rowc], d.cell_end[rowc + nc - 1]);
+                        continue;
+                    }
+                    int xl = -reach, xr = reach;
+                    while (xl < 0) {
+                        const double gx = gap(xl, cx, cw, ux);
+                        if (gx * gx + g2 <= rp2) break;
+                        ++xl;
+                    }
+                    while (xr > 0) {
+                        const double gx = gap(xr, cx, cw, ux);
+                        if (gx * gx + g2 <= rp2) break;
+                        --xr;
+                    }
+                    const int a = cx + xl, b = cx + xr;  // unwrapped cell range [a, b]
+                    if (a < 0) {
+                        scan(d.cell_start[rowc + a + nc], d.cell_end[rowc + nc - 1]);
+                        scan(d.cell_start[rowc], d.cell_end[rowc + b]);
+                    } else if (b >= nc) {
+                        scan(d.cell_start[rowc + a], d.cell_end[rowc + nc - 1]);
+                        scan(d.cell_start[rowc], d.cell_end[rowc + b - nc]);
+                    } else {
+                        scan(d.cell_start[rowc + a], d.cell_end[rowc + b]);
+                    }
+                }
+            }
+        }
+        total += cnt;
+        int kmax = wave_max_i(cnt);
+        kmax = (kmax + LIST_ROW_ALIGN - 1) / LIST_ROW_ALIGN * LIST_ROW_ALIGN;
+        for (int k = row + cnt; k < row + kmax && k < rows; ++k) col[(k >> 2) * 256 + (k & 3)] = s;
+        if (row + kmax > rows && lane == 0) set_err(d.err, KAMD_DEV_LIST_OVERFLOW);
+        kpart[tj] = kmax;
+        row += kmax;
+    }
+    if (row > rows) {  // keep the force kernels inside the list
+        kpart[0] = min(kpart[0], rows);
+        kpart[1] = min(kpart[1], rows - kpart[0]);
+    }
+    if (lane == 0) d.kmax[w] = make_int2(kpart[0], kpart[1]);
+    d.nlen[s] = total;
+}
+
+static inline int nblk_slots(const Dev &d) { return (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
+
+hipError_t launch_rb_assign(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rb_assign, dim3(nblk_slots(d)), dim3(BLOCK), 0, s, d);
+    return hipGetLastError();
+}
+hipError_t launch_rb_scan(const Dev &d, int nseg, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rb_scan, dim3(nseg), dim3(1024), 0, s, d);
+    return hipGetLastError();
+}
+hipError_t launch_rb_scatter(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rb_scatter, dim3(nblk_slots(d)), dim3(BLOCK), 0, s, d);
+    return hipGetLastError();
+}
+hipError_t launch_rb_sortgather(const Dev &d, hipStream_t s)
+{
+    const int nb = (d.ncells + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    hipLaunchKernelGGL(k_rb_sortgather, dim3(nb), dim3(BLOCK), 0, s, d);
+    return hipGetLastError();
+}
+hipError_t launch_rb_list(const Dev &d, int cell_div, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rb_list, dim3(nblk_slots(d)), dim3(BLOCK), 0, s, d, cell_div);
+    return hipGetLastError();
+}
+
+}  // namespace kamd

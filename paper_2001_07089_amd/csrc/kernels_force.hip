@@ -1,0 +1,250 @@
+// kernels_force.hip -- Kob-Andersen pair forces over the neighbour lists.
+//
+// Force on particle i, Eq. (KAFix): F_i = 48 sum_j eps_ab (sig_ab^12/r^14 -
+// 0.5 sig_ab^6/r^8)(r_i - r_j) over partners with r < 2.5 sig_ab (strict),
+// computed as 48 eps * s6 (s6 - 1/2) / r^2 with s6 = (sig^2/r^2)^3 so that no
+// square root is needed and the factor 48 eps is applied once per partner
+// type (the paper's own two savings, Sec. III.D).  With the energy flag the
+// shifted potential of Eq. (VshiftedKALJ), 4 eps s6 (s6 - 1) - V(r_c), and the
+// virial r.F = 48 eps s6 (s6 - 1/2) are accumulated too (each pair appears in
+// both partners' lists, so the per-particle sums are halved), together with
+// the number of (ordered) pairs inside the cutoff.
+//
+// One thread per particle; a wavefront holds 64 particles of one replica and
+// one type, so the parameters of each list part (A partners, then B partners,
+// the paper's type-split loops) are wavefront-uniform and live in scalar
+// registers.  Work is plain vector ALU arithmetic: a pair force is not a dense
+// contraction, so there is nothing for the matrix cores here.
+//
+// Precision variants (template PREC):
+//   0  FP64: binary64 separations with the minimum image taken as
+//      d - L rint(d/L), binary64 LJ terms and sums.
+//   1  MIXED: the separation is the exact integer difference of u32
+//      fixed-point coordinates (minimum image for free), converted to FP32;
+//      FP32 r^2, 1/r^2, LJ terms and per-part partial sums; the part sums are
+//      scaled to force units and added in FP64.
+//   2  MIXED_FIXED: as MIXED, but every pair force component is rounded to an
+//      integer number of 2^-26 force units (one FP64 fma against 1.5*2^52)
+//      and summed in 64-bit integers, so the sum is exact and independent of
+//      the order of the list; F_ij = -F_ji holds bit for bit.
+#include "common_dev.hpp"
+
+namespace kamd {
+
+// Close the rebuild check of the running step (every kernel of the rebuild
+// chain has finished reading it) and optionally advance the device step
+// counter.  Done by the first block of every force launch.
+__device__ inline void close_step(const Dev &d, int step_inc)
+{
+    if (blockIdx.x != 0) return;
+    for (int r = threadIdx.x; r < d.nrep; r += blockDim.x) {
+        d.maxdisp[r] = 0u;
+        d.rb_force[r] = 0;
+    }
+    if (step_inc && threadIdx.x == 0) d.counters[1] += 1;
+}
+
+__device__ inline double rcp_f64(double a)
+{
+    double y = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-a, y, 1.0);
+    return fma(y, e, y);
+}
+
+template <bool ENERGY>
+__global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_inc)
+{
+    close_step(d, step_inc);
+    const int w = wave_id_remapped();
+    if (w >= d.nwaves) return;
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    const RepInfo &R = d.rep[S.rep];
+    const int s = w * WAVE + lane_id();
+    const double L = R.L, invL = R.invL;
+    const double xi = d.x[s], yi = d.y[s], zi = d.z[s];
+    const int2 km = d.kmax[w];
+    double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, vir = 0.0, npair = 0.0;
+    int row = 0;
+#pragma unroll 1
+    for (int tj = 0; tj < 2; ++tj) {
+        const int p = S.type + tj;
+        const double rc2 = m.rc2[p], sig2 = m.sig2[p];
+        const int nrows = tj ? km.y : km.x;
+        double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, sv = 0.0;
+        int cnt = 0;
+        const int4 *nb = reinterpret_cast<const int4 *>(d.nbr + list_index(w, d.rows, row, lane_id()));
+        for (int k = 0; k < nrows; k += 4) {
+            const int4 q = nb[(k >> 2) * WAVE];
+            const int jj[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = jj[u];
+                double dx = xi - d.x[j];
+                double dy = yi - d.y[j];
+                double dz = zi - d.z[j];
+                dx = fma(-L, rint(dx * invL), dx);
+                dy = fma(-L, rint(dy * invL), dy);
+                dz = fma(-L, rint(dz * invL), dz);
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                const bool in = (r2 < rc2) && (r2 > 0.0);
+                const double ir2 = in ? rcp_f64(r2) : 0.0;
+                const double s2 = sig2 * ir2;
+                const double s6 = s2 * s2 * s2;
+                const double t = s6 * (s6 - 0.5);
+                const double f = t * ir2;
+                sx = fma(f, dx, sx);
+                sy = fma(f, dy, sy);
+                sz = fma(f, dz, sz);
+                if (ENERGY) {
+                    se += fma(-0.5, s6, t);
+                    sv += t;
+                    cnt += in ? 1 : 0;
+                }
+            }
+        }
+        const double e48 = 48.0 * m.eps[p];
+        fx = fma(e48, sx, fx);
+        fy = fma(e48, sy, fy);
+        fz = fma(e48, sz, fz);
+        if (ENERGY) {
+            pe += 0.5 * (4.0 * m.eps[p] * se - (double)cnt * m.vshift[p]);
+            vir += 0.5 * e48 * sv;
+            npair += (double)cnt;
+        }
+        row += nrows;
+    }
+    d.ax[s] = fx;
+    d.ay[s] = fy;
+    d.az[s] = fz;
+    if (!(isfinite(fx) && isfinite(fy) && isfinite(fz))) set_err(d.err, KAMD_DEV_NONFINITE);
+    if (ENERGY) {
+        pe = wave_sum(pe);
+        vir = wave_sum(vir);
+        npair = wave_sum(npair);
+        if (lane_id() == 0) {
+            d.wred[4 * w + 1] = pe;
+            d.wred[4 * w + 2] = vir;
+            d.wred[4 * w + 3] = npair;
+        }
+    }
+}
+
+template <bool FIXED, bool ENERGY>
+__global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_inc)
+{
+    close_step(d, step_inc);
+    const int w = wave_id_remapped();
+    if (w >= d.nwaves) return;
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    const RepInfo &R = d.rep[S.rep];
+    const int s = w * WAVE + lane_id();
+    const uint4 mi = d.mirror[s];
+    const int2 km = d.kmax[w];
+    double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, vir = 0.0, npair = 0.0;
+    uint64_t qx = 0, qy = 0, qz = 0;
+    int row = 0;
+#pragma unroll 1
+    for (int tj = 0; tj < 2; ++tj) {
+        const int p = S.type + tj;
+        const float rc2 = R.rc2_fx[p], sig2 = R.sig2_fx[p];
+        const double fk = R.fix_k[p];
+        const int nrows = tj ? km.y : km.x;
+        float sx = 0.0f, sy = 0.0f, sz = 0.0f, se = 0.0f, sv = 0.0f;
+        int cnt = 0;
+        const int4 *nb = reinterpret_cast<const int4 *>(d.nbr + list_index(w, d.rows, row, lane_id()));
+        for (int k = 0; k < nrows; k += 4) {
+            const int4 q = nb[(k >> 2) * WAVE];
+            const int jj[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint4 mj = d.mirror[jj[u]];
+                const int ix = (int)(mi.x - mj.x);
+                const int iy = (int)(mi.y - mj.y);
+                const int iz = (int)(mi.z - mj.z);
+                const float dx = (float)ix, dy = (float)iy, dz = (float)iz;
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const bool in = (r2 < rc2) && (r2 > 0.0f);
+                const float ir2 = in ? __builtin_amdgcn_rcpf(r2) : 0.0f;
+                const float s2 = sig2 * ir2;
+                const float s6 = s2 * s2 * s2;
+                const float t = s6 * (s6 - 0.5f);
+                const float f = t * ir2;
+                if (FIXED) {
+                    const double wd = (double)f * fk;
+                    qx += (uint64_t)__double_as_longlong(fma(wd, (double)ix, FIX_MAGIC));
+                    qy += (uint64_t)__double_as_longlong(fma(wd, (double)iy, FIX_MAGIC));
+                    qz += (uint64_t)__double_as_longlong(fma(wd, (double)iz, FIX_MAGIC));
+                } else {
+                    sx = fmaf(f, dx, sx);
+                    sy = fmaf(f, dy, sy);
+                    sz = fmaf(f, dz, sz);
+                }
+                if (ENERGY) {
+                    se += fmaf(-0.5f, s6, t);
+                    sv += t;
+                    cnt += in ? 1 : 0;
+                }
+            }
+        }
+        if (FIXED) {
+            const uint64_t mb = (uint64_t)__double_as_longlong(FIX_MAGIC) * (uint64_t)nrows;
+            qx -= mb;
+            qy -= mb;
+            qz -= mb;
+        } else {
+            const double c = R.c48_h[p];
+            fx = fma(c, (double)sx, fx);
+            fy = fma(c, (double)sy, fy);
+            fz = fma(c, (double)sz, fz);
+        }
+        if (ENERGY) {
+            pe += 0.5 * (4.0 * m.eps[p] * (double)se - (double)cnt * m.vshift[p]);
+            vir += 0.5 * 48.0 * m.eps[p] * (double)sv;
+            npair += (double)cnt;
+        }
+        row += nrows;
+    }
+    if (FIXED) {
+        const double inv = 1.0 / FIX_SCALE;
+        fx = (double)(int64_t)qx * inv;
+        fy = (double)(int64_t)qy * inv;
+        fz = (double)(int64_t)qz * inv;
+        const double lim = 1.0e8;
+        if (fabs(fx) > lim || fabs(fy) > lim || fabs(fz) > lim) set_err(d.err, KAMD_DEV_FORCE_RANGE);
+    }
+    d.ax[s] = fx;
+    d.ay[s] = fy;
+    d.az[s] = fz;
+    if (!(isfinite(fx) && isfinite(fy) && isfinite(fz))) set_err(d.err, KAMD_DEV_NONFINITE);
+    if (ENERGY) {
+        pe = wave_sum(pe);
+        vir = wave_sum(vir);
+        npair = wave_sum(npair);
+        if (lane_id() == 0) {
+            d.wred[4 * w + 1] = pe;
+            d.wred[4 * w + 2] = vir;
+            d.wred[4 * w + 3] = npair;
+        }
+    }
+}
+
+hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, bool step_inc, hipStream_t s)
+{
+    const int nb = (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    const int si = step_inc ? 1 : 0;
+    if (prec == 0) {
+        if (energy) hipLaunchKernelGGL(k_force_fp64<true>, dim3(nb), dim3(BLOCK), 0, s, d, m, si);
+        else hipLaunchKernelGGL(k_force_fp64<false>, dim3(nb), dim3(BLOCK), 0, s, d, m, si);
+    } else if (prec == 1) {
+        if (energy) hipLaunchKernelGGL((k_force_mixed<false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, si);
+        else hipLaunchKernelGGL((k_force_mixed<false, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si);
+    } else {
+        if (energy) hipLaunchKernelGGL((k_force_mixed<true, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, si);
+        else hipLaunchKernelGGL((k_force_mixed<true, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kamd

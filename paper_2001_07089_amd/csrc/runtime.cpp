@@ -1,0 +1,1174 @@
+// runtime.cpp -- host runtime of the Kob-Andersen MD library: the C ABI of
+// include/kamd.h, the replica/slot/cell layout, device memory, the step
+// loops, HIP graph capture, the list autotuner and checkpoints.
+#include "kamd.h"
+#include "kamd_internal.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+using namespace kamd;
+
+static std::string g_init_error = "no error";
+
+struct kamd_ctx {
+    kamd_config cfg{};
+    Model model{};
+    double rc_max = 0.0;
+    std::vector<kamd_replica> reps;
+    std::vector<SegInfo> segs;
+    std::vector<RepInfo> rinfo;
+    std::vector<int32_t> wave_seg, cell_seg;
+    std::vector<int32_t> rdf_block_rep, rdf_block_start;
+    kamd_state st{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Dev d{};
+    std::vector<void *> allocs;       // everything owned
+    void *cells_alloc[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // count, start, end, seg
+    void *nbr_alloc = nullptr;
+    int64_t rdf_cells_cap = 0;
+    double *Q_dev = nullptr;
+    double *obs_stage = nullptr;      // device [n_rep][4]
+    double *state_tmp = nullptr;      // device caller-order staging for checkpoints
+    int32_t *img_tmp = nullptr;
+    int64_t step = 0;
+    int64_t rebuilds_host = 0;
+    double skin = 0.3;
+    int cell_div = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int64_t graph_steps = 0;
+    std::string err = "no error";
+};
+
+// ------------------------------------------------------------------ errors
+static int fail(kamd_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else g_init_error = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, call)                                                                  \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail((ctx), KAMD_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// ------------------------------------------------------------------ layout
+static void model_from(const kamd_model &m, Model &out, double &rc_max)
+{
+    rc_max = 0.0;
+    for (int p = 0; p < 3; ++p) {
+        const double s = m.sigma[p];
+        const double rc = m.rc_factor * s;
+        out.eps[p] = m.eps[p];
+        out.sig2[p] = s * s;
+        out.rc2[p] = rc * rc;
+        const double sr2 = (s * s) / (rc * rc);
+        const double sr6 = sr2 * sr2 * sr2;
+        out.vshift[p] = 4.0 * m.eps[p] * (sr6 * sr6 - sr6);
+        rc_max = std::max(rc_max, rc);
+    }
+}
+
+static int validate(kamd_ctx *c, const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep)
+{
+    if (!cfg || !reps || n_rep <= 0) return fail(c, KAMD_EINVAL, "null config/replicas or n_rep <= 0");
+    if (cfg->precision < 0 || cfg->precision > 2) return fail(c, KAMD_EINVAL, "bad precision %d", cfg->precision);
+    if (!(cfg->dt > 0.0)) return fail(c, KAMD_EINVAL, "dt must be > 0");
+    if (cfg->cell_div < 0 || cfg->cell_div > 2) return fail(c, KAMD_EINVAL, "cell_div must be 0, 1 or 2");
+    if (!(cfg->model.rc_factor > 0.0)) return fail(c, KAMD_EINVAL, "rc_factor must be > 0");
+    for (int p = 0; p < 3; ++p)
+        if (!(cfg->model.sigma[p] > 0.0) || !std::isfinite(cfg->model.eps[p]))
+            return fail(c, KAMD_EINVAL, "bad model parameters for pair %d", p);
+    Model m;
+    double rcmax;
+    model_from(cfg->model, m, rcmax);
+    int64_t expect_off = 0;
+    for (int r = 0; r < n_rep; ++r) {
+        const kamd_replica &R = reps[r];
+        if (R.n <= 0 || R.n_a < 0 || R.n_a > R.n) return fail(c, KAMD_EINVAL, "replica %d: bad n=%d n_a=%d", r, R.n, R.n_a);
+        if (R.offset != expect_off) return fail(c, KAMD_EINVAL, "replica %d: offset %lld, expected %lld (contiguous)", r, (long long)R.offset, (long long)expect_off);
+        if (!(R.box > 0.0) || !std::isfinite(R.box)) return fail(c, KAMD_EINVAL, "replica %d: bad box", r);
+        if (!(R.temperature >= 0.0)) return fail(c, KAMD_EINVAL, "replica %d: bad temperature", r);
+        if (!(rcmax < 0.5 * R.box)) return fail(c, KAMD_EBOX, "replica %d: largest cutoff %.6g >= L/2 = %.6g", r, rcmax, 0.5 * R.box);
+        expect_off += R.n;
+    }
+    if (expect_off > (int64_t)1 << 30) return fail(c, KAMD_EINVAL, "too many particles");
+    return KAMD_OK;
+}
+
+struct Plan {
+    std::vector<SegInfo> segs;
+    std::vector<RepInfo> rinfo;
+    std::vector<int32_t> wave_seg, cell_seg;
+    int32_t npad = 0, nwaves = 0, ncells = 0, rows = 0, n_total = 0;
+};
+
+static double list_skin(const kamd_config *cfg) { return cfg->skin < 0.0 ? 0.3 : cfg->skin; }
+
+static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_rep, double skin, int cell_div,
+                      Plan &P)
+{
+    Model m;
+    double rcmax;
+    model_from(cfg->model, m, rcmax);
+    const int reach = cell_div <= 0 ? 1 : cell_div;
+    const double rlist = rcmax + skin;
+    const double cap = cfg->list_capacity > 0.0 ? cfg->list_capacity : 1.6;
+    P = Plan();
+    int32_t slot = 0, cell = 0;
+    double rows_need = 0.0;
+    for (int r = 0; r < n_rep; ++r) {
+        const kamd_replica &K = reps[r];
+        RepInfo R;
+        std::memset(&R, 0, sizeof R);
+        R.L = K.box;
+        R.invL = 1.0 / K.box;
+        R.T = K.temperature;
+        R.seed = K.seed;
+        R.caller_off = K.offset;
+        R.n = K.n;
+        R.na = K.n_a;
+        R.skin = skin;
+        const double half = 0.5 * skin;
+        R.disp_thr2 = half * half * (1.0 - 1e-5);
+        int nc = (int)std::floor(K.box * reach / rlist);
+        nc = std::max(1, std::min(nc, 1024));
+        R.nc = nc;
+        const double h = K.box / 4294967296.0;
+        for (int p = 0; p < 3; ++p) {
+            const double rc = cfg->model.rc_factor * cfg->model.sigma[p];
+            const double rl = rc + skin;
+            R.rc2_fx[p] = (float)((rc / h) * (rc / h));
+            R.rl2_fx[p] = (float)((rl / h) * (rl / h) * (1.0 + 4e-6));
+            R.sig2_fx[p] = (float)((cfg->model.sigma[p] / h) * (cfg->model.sigma[p] / h));
+            R.c48_h[p] = 48.0 * cfg->model.eps[p] / h;
+            R.fix_k[p] = R.c48_h[p] * FIX_SCALE;
+        }
+        R.fx_to_len = h;
+        R.wave0 = slot / WAVE;
+        for (int t = 0; t < 2; ++t) {
+            SegInfo S;
+            std::memset(&S, 0, sizeof S);
+            S.rep = r;
+            S.type = t;
+            S.slot0 = slot;
+            S.n = t == 0 ? K.n_a : K.n - K.n_a;
+            S.npad = (S.n + WAVE - 1) / WAVE * WAVE;
+            S.cell0 = cell;
+            S.ncell = nc * nc * nc;
+            R.seg[t] = (int32_t)P.segs.size();
+            for (int w = 0; w < S.npad / WAVE; ++w) P.wave_seg.push_back(R.seg[t]);
+            for (int c = 0; c < S.ncell; ++c) P.cell_seg.push_back(R.seg[t]);
+            slot += S.npad;
+            cell += S.ncell;
+            P.segs.push_back(S);
+        }
+        R.wave1 = slot / WAVE;
+        P.rinfo.push_back(R);
+        // expected list rows: wavefront maxima of the A part and the B part
+        const double V = K.box * K.box * K.box;
+        const double rhoA = K.n_a / V, rhoB = (K.n - K.n_a) / V;
+        const double pi43 = 4.0 / 3.0 * M_PI;
+        auto vol = [&](int p) { double rl = cfg->model.rc_factor * cfg->model.sigma[p] + skin; return pi43 * rl * rl * rl; };
+        const double rowsA = std::max(K.n_a > 0 ? rhoA * vol(0) + rhoB * vol(1) : 0.0,
+                                      K.n > K.n_a ? rhoA * vol(1) + rhoB * vol(2) : 0.0);
+        rows_need = std::max(rows_need, rowsA);
+        P.n_total += K.n;
+    }
+    P.npad = slot;
+    P.nwaves = slot / WAVE;
+    P.ncells = cell;
+    int rows = (int)std::ceil(cap * rows_need) + 32;
+    rows = (rows + LIST_ROW_ALIGN - 1) / LIST_ROW_ALIGN * LIST_ROW_ALIGN;
+    P.rows = rows;
+}
+
+// Bytes of device memory for a plan.
+static size_t plan_bytes(const Plan &P, int n_rep)
+{
+    const size_t np = P.npad, nt = P.n_total;
+    size_t b = 0;
+    b += 2 * (9 * 8 + 3 * 4 + 4 + 16) * np;  // state + scratch
+    b += 16 * np;                              // mbuild
+    b += 4 * np * 3;                           // cell_of, rank, order
+    b += 4 * np;                               // nlen
+    b += 4 * (size_t)P.ncells * 2;             // count/start
+    b += 4 * (size_t)P.rows * np;              // neighbour list
+    b += (8 + 4 + 32) * (size_t)P.nwaves;      // kmax, disp, wred
+    b += (sizeof(SegInfo) + sizeof(RepInfo)) * 2 * (size_t)n_rep + 4 * (P.nwaves + P.ncells);
+    b += 3 * 8 * nt;                           // one MSD origin (more on demand)
+    return b;
+}
+
+extern "C" int md_workspace_size(const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep, size_t *bytes)
+{
+    int rc = validate(nullptr, cfg, reps, n_rep);
+    if (rc) return rc;
+    if (!bytes) return fail(nullptr, KAMD_EINVAL, "bytes is null");
+    Plan P;
+    make_plan(cfg, reps, n_rep, list_skin(cfg), cfg->cell_div <= 0 ? 1 : cfg->cell_div, P);
+    *bytes = plan_bytes(P, n_rep);
+    return KAMD_OK;
+}
+
+extern "C" int md_admit(const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep, size_t budget,
+                        int32_t *admitted, int32_t *n_admitted)
+{
+    if (!cfg || !reps || n_rep <= 0 || !admitted) return fail(nullptr, KAMD_EINVAL, "bad arguments to md_admit");
+    size_t used = 0;
+    int cnt = 0;
+    std::vector<kamd_replica> acc;
+    for (int r = 0; r < n_rep; ++r) {
+        kamd_replica k = reps[r];
+        k.offset = 0;
+        for (auto &a : acc) k.offset += a.n;
+        acc.push_back(k);
+        Plan P;
+        int v = validate(nullptr, cfg, acc.data(), (int)acc.size());
+        size_t b = 0;
+        if (v == KAMD_OK) {
+            make_plan(cfg, acc.data(), (int)acc.size(), list_skin(cfg), cfg->cell_div <= 0 ? 1 : cfg->cell_div, P);
+            b = plan_bytes(P, (int)acc.size());
+        }
+        if (v == KAMD_OK && b <= budget) {
+            admitted[r] = 1;
+            used = b;
+            ++cnt;
+        } else {
+            admitted[r] = 0;
+            acc.pop_back();
+        }
+    }
+    (void)used;
+    if (n_admitted) *n_admitted = cnt;
+    return KAMD_OK;
+}
+
+// ------------------------------------------------------------------ memory
+template <typename T>
+static int dalloc(kamd_ctx *c, T **p, size_t count)
+{
+    void *q = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&q, count * sizeof(T));
+    if (e != hipSuccess) return fail(c, KAMD_ENOMEM, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
+    c->allocs.push_back(q);
+    *p = (T *)q;
+    return KAMD_OK;
+}
+
+static void dfree(kamd_ctx *c, void *p)
+{
+    if (!p) return;
+    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+    if (it != c->allocs.end()) c->allocs.erase(it);
+    (void)hipFree(p);
+}
+
+#define TRY(x)                 \
+    do {                       \
+        int r_ = (x);          \
+        if (r_) return r_;     \
+    } while (0)
+
+static int upload_tables(kamd_ctx *c)
+{
+    Dev &d = c->d;
+    HIPCHK(c, hipMemcpyAsync((void *)d.seg, c->segs.data(), sizeof(SegInfo) * c->segs.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((void *)d.rep, c->rinfo.data(), sizeof(RepInfo) * c->rinfo.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((void *)d.wave_seg, c->wave_seg.data(), 4 * c->wave_seg.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync((void *)d.cell_seg, c->cell_seg.data(), 4 * c->cell_seg.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KAMD_OK;
+}
+
+static void drop_graph(kamd_ctx *c)
+{
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+    c->graph_steps = 0;
+}
+
+// (Re)allocate what depends on the list parameters: cell arrays, cell->segment
+// table and the neighbour list.
+static int alloc_list_buffers(kamd_ctx *c, const Plan &P)
+{
+    Dev &d = c->d;
+    for (int k = 0; k < 5; ++k) {
+        dfree(c, c->cells_alloc[k]);
+        c->cells_alloc[k] = nullptr;
+    }
+    dfree(c, c->nbr_alloc);
+    c->nbr_alloc = nullptr;
+    int32_t *cc, *cs, *ce, *csg;
+    TRY(dalloc(c, &cc, P.ncells));
+    TRY(dalloc(c, &cs, P.ncells));
+    TRY(dalloc(c, &ce, P.ncells));
+    TRY(dalloc(c, &csg, P.ncells));
+    c->cells_alloc[0] = cc;
+    c->cells_alloc[1] = cs;
+    c->cells_alloc[2] = ce;
+    c->cells_alloc[3] = csg;
+    d.cell_count = cc;
+    d.cell_start = cs;
+    d.cell_end = ce;
+    d.cell_seg = csg;
+    int32_t *nb;
+    TRY(dalloc(c, &nb, (size_t)P.rows * P.npad));
+    c->nbr_alloc = nb;
+    d.nbr = nb;
+    d.rows = P.rows;
+    d.ncells = P.ncells;
+    HIPCHK(c, launch_zero_i32(cc, P.ncells, c->stream));
+    HIPCHK(c, launch_zero_i32(nb, (int64_t)P.rows * P.npad, c->stream));
+    return KAMD_OK;
+}
+
+static int alloc_all(kamd_ctx *c, const Plan &P)
+{
+    Dev &d = c->d;
+    const size_t np = P.npad;
+    d.npad_total = P.npad;
+    d.n_total = P.n_total;
+    d.nwaves = P.nwaves;
+    d.nrep = (int32_t)c->reps.size();
+    double **f64[] = {&d.x, &d.y, &d.z, &d.vx, &d.vy, &d.vz, &d.ax, &d.ay, &d.az,
+                      &d.sx, &d.sy, &d.sz, &d.svx, &d.svy, &d.svz, &d.sax, &d.say, &d.saz};
+    for (auto p : f64) TRY(dalloc(c, p, np));
+    TRY(dalloc(c, &d.img, 3 * np));
+    TRY(dalloc(c, &d.simg, 3 * np));
+    TRY(dalloc(c, &d.id, np));
+    TRY(dalloc(c, &d.sid, np));
+    TRY(dalloc(c, &d.mirror, np));
+    TRY(dalloc(c, &d.mbuild, np));
+    TRY(dalloc(c, &d.smirror, np));
+    SegInfo *sg;
+    RepInfo *ri;
+    int32_t *ws;
+    TRY(dalloc(c, &sg, c->segs.size()));
+    TRY(dalloc(c, &ri, c->rinfo.size()));
+    TRY(dalloc(c, &ws, P.nwaves));
+    d.seg = sg;
+    d.rep = ri;
+    d.wave_seg = ws;
+    TRY(dalloc(c, &d.cell_of, np));
+    TRY(dalloc(c, &d.rank, np));
+    TRY(dalloc(c, &d.order, np));
+    TRY(dalloc(c, &d.nlen, np));
+    TRY(dalloc(c, &d.rb_force, d.nrep));
+    TRY(dalloc(c, &d.maxdisp, d.nrep));
+    TRY(dalloc(c, &d.kmax, P.nwaves));
+    TRY(dalloc(c, &d.wred, 4 * (size_t)P.nwaves));
+    TRY(dalloc(c, &d.rsum, 4 * (size_t)d.nrep));
+    TRY(dalloc(c, &d.obs, 8 * (size_t)d.nrep));
+    TRY(dalloc(c, &d.dyn, d.nrep));
+    TRY(dalloc(c, &d.err, 4));
+    TRY(dalloc(c, &d.counters, 8));
+    TRY(dalloc(c, &c->Q_dev, d.nrep));
+    TRY(dalloc(c, &c->obs_stage, 4 * (size_t)d.nrep));
+    // zero everything that is read before written
+    for (auto p : f64) HIPCHK(c, launch_zero_f64(*p, np, c->stream));
+    HIPCHK(c, launch_zero_i32(d.img, 3 * np, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.mirror, 4 * np, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.mbuild, 4 * np, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.smirror, 4 * np, c->stream));
+    HIPCHK(c, launch_zero_i32(d.nlen, np, c->stream));
+    HIPCHK(c, launch_zero_i32(d.rb_force, d.nrep, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.maxdisp, d.nrep, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.kmax, 2 * (int64_t)P.nwaves, c->stream));
+    HIPCHK(c, launch_zero_f64(d.wred, 4 * (int64_t)P.nwaves, c->stream));
+    HIPCHK(c, launch_zero_f64((double *)d.dyn, 8 * (int64_t)d.nrep, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.err, 4, c->stream));
+    HIPCHK(c, launch_zero_i32(d.counters, 8, c->stream));
+    TRY(alloc_list_buffers(c, P));
+    return KAMD_OK;
+}
+
+// ---------------------------------------------------------- initial states
+// Random sequential addition: uniform proposals, accepted when no placed
+// particle is closer than dmin (minimum image); the first n_a accepted are A.
+// Falls back to the lattice when the attempt budget runs out.
+static bool rsa_positions(const kamd_replica &K, double dmin, std::vector<double> &x, std::vector<double> &y,
+                          std::vector<double> &z)
+{
+    const int n = K.n;
+    const double L = K.box;
+    std::mt19937_64 rng(K.seed ^ 0x5253414b414d4431ull);
+    std::uniform_real_distribution<double> U(0.0, L);
+    int nc = std::max(1, (int)std::floor(L / dmin));
+    if (nc < 3) nc = 1;
+    const double cw = L / nc;
+    std::vector<int> head((size_t)nc * nc * nc, -1), next(n, -1);
+    x.resize(n);
+    y.resize(n);
+    z.resize(n);
+    const double d2 = dmin * dmin;
+    int placed = 0;
+    const int64_t budget = (int64_t)n * 4000 + 100000;
+    int64_t tries = 0;
+    auto mi = [L](double d) { if (d > 0.5 * L) d -= L; else if (d < -0.5 * L) d += L; return d; };
+    while (placed < n && tries < budget) {
+        ++tries;
+        double px = U(rng), py = U(rng), pz = U(rng);
+        int cx = std::min(nc - 1, (int)(px / cw)), cy = std::min(nc - 1, (int)(py / cw)), cz = std::min(nc - 1, (int)(pz / cw));
+        bool ok = true;
+        const int lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : 0;
+        for (int oz = lo; oz <= hi && ok; ++oz)
+            for (int oy = lo; oy <= hi && ok; ++oy)
+                for (int ox = lo; ox <= hi && ok; ++ox) {
+                    int q = (((cz + oz + nc) % nc) * nc + (cy + oy + nc) % nc) * nc + (cx + ox + nc) % nc;
+                    for (int j = head[q]; j >= 0; j = next[j]) {
+                        double dx = mi(px - x[j]), dy = mi(py - y[j]), dz = mi(pz - z[j]);
+                        if (dx * dx + dy * dy + dz * dz < d2) { ok = false; break; }
+                    }
+                }
+        if (!ok) continue;
+        x[placed] = px;
+        y[placed] = py;
+        z[placed] = pz;
+        int q = (cz * nc + cy) * nc + cx;
+        next[placed] = head[q];
+        head[q] = placed;
+        ++placed;
+    }
+    return placed == n;
+}
+
+// Simple cubic lattice sites (0.5 + k) L/m, then each B particle swaps its
+// site with a randomly chosen A particle (Sec. III.A).
+static void lattice_positions(const kamd_replica &K, std::vector<double> &x, std::vector<double> &y,
+                              std::vector<double> &z)
+{
+    const int n = K.n;
+    int m = (int)std::ceil(std::cbrt((double)n) - 1e-9);
+    while ((int64_t)m * m * m < n) ++m;
+    const double a = K.box / m;
+    x.resize(n);
+    y.resize(n);
+    z.resize(n);
+    for (int i = 0; i < n; ++i) {
+        x[i] = (0.5 + i % m) * a;
+        y[i] = (0.5 + (i / m) % m) * a;
+        z[i] = (0.5 + i / (m * m)) * a;
+    }
+    std::mt19937_64 rng(K.seed ^ 0x4c41545449434531ull);
+    if (K.n_a > 0)
+        for (int i = K.n_a; i < n; ++i) {
+            std::uniform_int_distribution<int> D(0, K.n_a - 1);
+            int j = D(rng);
+            std::swap(x[i], x[j]);
+            std::swap(y[i], y[j]);
+            std::swap(z[i], z[j]);
+        }
+}
+
+// ---------------------------------------------------------------- kernels
+static int rebuild_chain(kamd_ctx *c)
+{
+    const Dev &d = c->d;
+    HIPCHK(c, launch_rb_assign(d, c->stream));
+    HIPCHK(c, launch_rb_scan(d, (int)c->segs.size(), c->stream));
+    HIPCHK(c, launch_rb_scatter(d, c->stream));
+    HIPCHK(c, launch_rb_sortgather(d, c->stream));
+    HIPCHK(c, launch_rb_list(d, c->cell_div, c->stream));
+    return KAMD_OK;
+}
+
+static int force_rebuild_all(kamd_ctx *c)
+{
+    std::vector<int32_t> ones(c->reps.size(), 1);
+    HIPCHK(c, hipMemcpyAsync(c->d.rb_force, ones.data(), 4 * ones.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KAMD_OK;
+}
+
+static int forces(kamd_ctx *c, bool energy)
+{
+    TRY(rebuild_chain(c));
+    HIPCHK(c, launch_force(c->d, c->model, c->cfg.precision, energy, false, c->stream));
+    return KAMD_OK;
+}
+
+static int mb_reassign(kamd_ctx *c, bool device_tag, uint32_t tag)
+{
+    const Dev &d = c->d;
+    if (device_tag) HIPCHK(c, launch_mb_draw_dev(d, c->stream));
+    else HIPCHK(c, launch_mb_draw(d, tag, c->stream));
+    HIPCHK(c, launch_rep_reduce(d, 7, c->stream));
+    HIPCHK(c, launch_mb_center(d, c->stream));
+    HIPCHK(c, launch_rep_reduce(d, 1, c->stream));
+    HIPCHK(c, launch_mb_scale(d, c->stream));
+    return KAMD_OK;
+}
+
+static int do_export(kamd_ctx *c)
+{
+    double *a[9] = {c->st.x, c->st.y, c->st.z, c->st.vx, c->st.vy, c->st.vz, c->st.ax, c->st.ay, c->st.az};
+    HIPCHK(c, launch_export(c->d, a, c->st.img, c->stream));
+    return KAMD_OK;
+}
+
+static int maybe_export(kamd_ctx *c) { return c->cfg.auto_sync ? do_export(c) : KAMD_OK; }
+
+// Enqueue nsteps steps.  ensemble 0: NVE; 1: NVT with mode/nb/tau.
+// device_tags: the Maxwell-Boltzmann draw tags come from the device step
+// counter (graph replays), else from the host counter.
+static int enqueue_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb, bool device_tags)
+{
+    const Dev &d = c->d;
+    const double dt = c->cfg.dt;
+    const int prec = c->cfg.precision;
+    if (ensemble == 1 && mode == KAMD_NVT_NOSE_HOOVER) {
+        HIPCHK(c, launch_ke_partial(d, c->stream));
+        HIPCHK(c, launch_rep_reduce(d, 1, c->stream));
+        HIPCHK(c, launch_set_k2(d, c->stream));
+        for (int s = 1; s <= nsteps; ++s) {
+            HIPCHK(c, launch_nh_begin(d, dt, c->Q_dev, c->stream));
+            HIPCHK(c, launch_drift_nh(d, dt, c->stream));
+            TRY(rebuild_chain(c));
+            HIPCHK(c, launch_force(d, c->model, prec, false, true, c->stream));
+            HIPCHK(c, launch_kick_nh(d, c->stream));
+            HIPCHK(c, launch_rep_reduce(d, 1, c->stream));
+            HIPCHK(c, launch_nh_end(d, dt, c->Q_dev, c->stream));
+        }
+        return KAMD_OK;
+    }
+    const bool stoch = ensemble == 1 && mode == KAMD_NVT_STOCHASTIC;
+    bool need_drift = true;
+    for (int s = 1; s <= nsteps; ++s) {
+        if (need_drift) HIPCHK(c, launch_drift(d, dt, c->stream));
+        TRY(rebuild_chain(c));
+        HIPCHK(c, launch_force(d, c->model, prec, false, true, c->stream));
+        const int64_t gstep = c->step + s;
+        const bool reassign = stoch && nb > 0 && (gstep % nb) == 0;
+        if (s == nsteps || reassign) {
+            HIPCHK(c, launch_kick_nve(d, dt, false, c->stream));
+            if (reassign) TRY(mb_reassign(c, device_tags, (uint32_t)gstep));
+            need_drift = true;
+        } else {
+            HIPCHK(c, launch_kick_drift(d, dt, false, c->stream));
+            need_drift = false;
+        }
+    }
+    return KAMD_OK;
+}
+
+static int set_Q(kamd_ctx *c, double tau)
+{
+    std::vector<double> Q(c->reps.size());
+    for (size_t r = 0; r < Q.size(); ++r) {
+        Q[r] = 3.0 * c->reps[r].n * c->reps[r].temperature * tau * tau;
+        if (!(Q[r] > 0.0)) return fail(c, KAMD_EINVAL, "Nose-Hoover bath mass Q = 3 N T tau^2 must be > 0 (replica %zu)", r);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->Q_dev, Q.data(), 8 * Q.size(), hipMemcpyHostToDevice, c->stream));
+    return KAMD_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" const char *md_last_error(const kamd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
+
+static int apply_list_params(kamd_ctx *c, double skin, int cell_div, bool first)
+{
+    if (!(skin >= 0.0)) return fail(c, KAMD_EINVAL, "skin must be >= 0");
+    if (cell_div < 1 || cell_div > 2) return fail(c, KAMD_EINVAL, "cell_div must be 1 or 2");
+    Plan P;
+    make_plan(&c->cfg, c->reps.data(), (int)c->reps.size(), skin, cell_div, P);
+    c->skin = skin;
+    c->cell_div = cell_div;
+    c->segs = P.segs;
+    c->rinfo = P.rinfo;
+    c->wave_seg = P.wave_seg;
+    c->cell_seg = P.cell_seg;
+    if (!first) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        TRY(alloc_list_buffers(c, P));
+        TRY(upload_tables(c));
+        TRY(force_rebuild_all(c));
+        drop_graph(c);
+    }
+    return KAMD_OK;
+}
+
+extern "C" int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
+                       const kamd_state *st, void *hip_stream)
+{
+    if (!out) return fail(nullptr, KAMD_EINVAL, "out is null");
+    *out = nullptr;
+    int rc = validate(nullptr, cfg, reps, n_rep);
+    if (rc) return rc;
+    if (!st) return fail(nullptr, KAMD_EINVAL, "state is null");
+    if (cfg->init_mode == KAMD_INIT_GIVEN && (!st->x || !st->y || !st->z || !st->vx || !st->vy || !st->vz))
+        return fail(nullptr, KAMD_EINVAL, "KAMD_INIT_GIVEN needs x, y, z, vx, vy, vz");
+    if (cfg->init_mode < 0 || cfg->init_mode > 2) return fail(nullptr, KAMD_EINVAL, "bad init_mode");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return fail(nullptr, KAMD_EHIP, "no HIP device available");
+    kamd_ctx *c = new kamd_ctx();
+    c->cfg = *cfg;
+    c->reps.assign(reps, reps + n_rep);
+    c->st = *st;
+    c->stream = (hipStream_t)hip_stream;
+    (void)hipGetDevice(&c->device);
+    model_from(cfg->model, c->model, c->rc_max);
+    int r = [&]() -> int {
+        TRY(apply_list_params(c, list_skin(cfg), cfg->cell_div <= 0 ? 1 : cfg->cell_div, true));
+        Plan P;
+        make_plan(&c->cfg, c->reps.data(), n_rep, c->skin, c->cell_div, P);
+        TRY(alloc_all(c, P));
+        TRY(upload_tables(c));
+        // slot -> caller index
+        std::vector<int32_t> ids(P.npad, -1);
+        for (const SegInfo &S : c->segs) {
+            const kamd_replica &K = c->reps[S.rep];
+            const int64_t first = K.offset + (S.type == 0 ? 0 : K.n_a);
+            for (int i = 0; i < S.n; ++i) ids[S.slot0 + i] = (int32_t)(first + i);
+        }
+        HIPCHK(c, hipMemcpyAsync(c->d.id, ids.data(), 4 * ids.size(), hipMemcpyHostToDevice, c->stream));
+        // RDF block table
+        for (int q = 0; q < n_rep; ++q)
+            for (int i = 0; i < c->reps[q].n; i += BLOCK) {
+                c->rdf_block_rep.push_back(q);
+                c->rdf_block_start.push_back((int32_t)(c->reps[q].offset + i));
+            }
+        int32_t *brep, *bst;
+        TRY(dalloc(c, &brep, c->rdf_block_rep.size()));
+        TRY(dalloc(c, &bst, c->rdf_block_start.size()));
+        HIPCHK(c, hipMemcpyAsync(brep, c->rdf_block_rep.data(), 4 * c->rdf_block_rep.size(), hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(bst, c->rdf_block_start.data(), 4 * c->rdf_block_start.size(), hipMemcpyHostToDevice, c->stream));
+        c->d.rdf_block_rep = brep;
+        c->d.rdf_block_start = bst;
+        TRY(dalloc(c, &c->d.origin, 16 * 3 * (size_t)P.n_total));
+        const int64_t nt = P.n_total;
+        if (cfg->init_mode == KAMD_INIT_GIVEN) {
+            const double *a[9] = {st->x, st->y, st->z, st->vx, st->vy, st->vz, nullptr, nullptr, nullptr};
+            HIPCHK(c, launch_import(c->d, a, st->img, c->stream));
+        } else {
+            std::vector<double> hx(nt), hy(nt), hz(nt);
+            for (int q = 0; q < n_rep; ++q) {
+                const kamd_replica &K = c->reps[q];
+                std::vector<double> x, y, z;
+                bool ok = false;
+                if (cfg->init_mode == KAMD_INIT_RSA) ok = rsa_positions(K, cfg->min_dist > 0 ? cfg->min_dist : 0.8, x, y, z);
+                if (!ok) lattice_positions(K, x, y, z);
+                std::copy(x.begin(), x.end(), hx.begin() + K.offset);
+                std::copy(y.begin(), y.end(), hy.begin() + K.offset);
+                std::copy(z.begin(), z.end(), hz.begin() + K.offset);
+            }
+            double *tmp;
+            TRY(dalloc(c, &tmp, 3 * (size_t)nt));
+            HIPCHK(c, hipMemcpyAsync(tmp, hx.data(), 8 * nt, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(tmp + nt, hy.data(), 8 * nt, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hipMemcpyAsync(tmp + 2 * nt, hz.data(), 8 * nt, hipMemcpyHostToDevice, c->stream));
+            const double *a[9] = {tmp, tmp + nt, tmp + 2 * nt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+            HIPCHK(c, launch_import(c->d, a, nullptr, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            dfree(c, tmp);
+            TRY(mb_reassign(c, false, 0u));
+        }
+        TRY(force_rebuild_all(c));
+        TRY(forces(c, false));
+        TRY(do_export(c));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return KAMD_OK;
+    }();
+    if (r) {
+        g_init_error = c->err;
+        md_destroy(c);
+        return r;
+    }
+    *out = c;
+    return KAMD_OK;
+}
+
+extern "C" int md_build_cells(kamd_ctx *c)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    TRY(force_rebuild_all(c));
+    TRY(rebuild_chain(c));
+    return KAMD_OK;
+}
+
+extern "C" int md_forces(kamd_ctx *c, uint32_t flags, double *obs_dev)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    const bool energy = (flags & (KAMD_F_ENERGY | KAMD_F_VIRIAL)) != 0;
+    if (energy && !obs_dev) return fail(c, KAMD_EINVAL, "energy/virial requested without obs_dev");
+    TRY(forces(c, energy));
+    if (energy) {
+        HIPCHK(c, launch_rep_reduce(c->d, 6, c->stream));
+        HIPCHK(c, launch_store_pe_w(c->d, obs_dev, c->stream));
+    }
+    return maybe_export(c);
+}
+
+extern "C" int md_step_nve(kamd_ctx *c, int32_t nsteps)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (nsteps < 0) return fail(c, KAMD_EINVAL, "nsteps < 0");
+    if (nsteps == 0) return KAMD_OK;
+    TRY(enqueue_steps(c, nsteps, 0, 0, 0, false));
+    c->step += nsteps;
+    return maybe_export(c);
+}
+
+extern "C" int md_step_nvt(kamd_ctx *c, int32_t nsteps, int32_t mode, int32_t n_reassign, double tau)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (nsteps < 0) return fail(c, KAMD_EINVAL, "nsteps < 0");
+    if (mode == KAMD_NVT_STOCHASTIC) {
+        if (n_reassign <= 0) return fail(c, KAMD_EINVAL, "n_reassign must be > 0");
+    } else if (mode == KAMD_NVT_NOSE_HOOVER) {
+        if (!(tau > 0.0)) return fail(c, KAMD_EINVAL, "tau must be > 0");
+        TRY(set_Q(c, tau));
+    } else {
+        return fail(c, KAMD_EINVAL, "bad thermostat mode %d", mode);
+    }
+    if (nsteps == 0) return KAMD_OK;
+    TRY(enqueue_steps(c, nsteps, 1, mode, n_reassign, false));
+    c->step += nsteps;
+    return maybe_export(c);
+}
+
+extern "C" int md_rdf(kamd_ctx *c, double dr, int32_t n_bins, uint64_t *hist_dev)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (!(dr > 0.0) || n_bins <= 0 || !hist_dev) return fail(c, KAMD_EINVAL, "bad RDF arguments");
+    if (3 * (size_t)n_bins * 4 > 60 * 1024) return fail(c, KAMD_EINVAL, "n_bins too large (max 5120)");
+    const double rmax = n_bins * dr;
+    int64_t cells = 0;
+    for (size_t r = 0; r < c->reps.size(); ++r) {
+        const double L = c->reps[r].box;
+        if (rmax > 0.5 * L * (1.0 + 1e-12)) return fail(c, KAMD_EINVAL, "n_bins*dr = %.9g exceeds L/2 = %.9g (replica %zu)", rmax, 0.5 * L, r);
+        int nc = std::max(1, (int)std::floor(L / rmax));
+        nc = std::min(nc, 512);
+        c->rinfo[r].rdf_nc = nc;
+        c->rinfo[r].rdf_cell0 = (int32_t)cells;
+        c->rinfo[r].rdf_ncell = nc * nc * nc;
+        cells += (int64_t)nc * nc * nc;
+    }
+    Dev &d = c->d;
+    if (cells > c->rdf_cells_cap) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        dfree(c, d.rdf_count);
+        dfree(c, d.rdf_start);
+        TRY(dalloc(c, &d.rdf_count, cells));
+        TRY(dalloc(c, &d.rdf_start, cells));
+        c->rdf_cells_cap = cells;
+        if (!d.rdf_cell_of) {
+            TRY(dalloc(c, &d.rdf_cell_of, d.npad_total));
+            TRY(dalloc(c, &d.rdf_rank, d.npad_total));
+            TRY(dalloc(c, &d.rdf_pos, d.n_total));
+        }
+        drop_graph(c);
+    }
+    HIPCHK(c, hipMemcpyAsync((void *)d.rep, c->rinfo.data(), sizeof(RepInfo) * c->rinfo.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_zero_i32(d.rdf_count, cells, c->stream));
+    HIPCHK(c, launch_rdf_prepare(d, c->stream));
+    HIPCHK(c, launch_rdf(d, dr, n_bins, (int)c->rdf_block_rep.size(), hist_dev, c->stream));
+    // the RepInfo copy must stay alive until the copy has been consumed
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KAMD_OK;
+}
+
+extern "C" int md_msd(kamd_ctx *c, int32_t op, int32_t slot, double *out_dev)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (slot < 0 || slot >= 16) return fail(c, KAMD_EINVAL, "origin slot must be in [0, 16)");
+    if (op == 0) {
+        HIPCHK(c, launch_msd_set(c->d, slot, c->stream));
+    } else if (op == 1) {
+        if (!out_dev) return fail(c, KAMD_EINVAL, "out_dev is null");
+        HIPCHK(c, launch_msd_measure(c->d, slot, c->stream));
+        HIPCHK(c, launch_rep_reduce(c->d, 3, c->stream));
+        HIPCHK(c, launch_msd_finish(c->d, out_dev, c->stream));
+    } else {
+        return fail(c, KAMD_EINVAL, "op must be 0 (SET_ORIGIN) or 1 (MEASURE)");
+    }
+    return KAMD_OK;
+}
+
+extern "C" int md_observables(kamd_ctx *c, double *host_out)
+{
+    if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");
+    const size_t nr = c->reps.size();
+    HIPCHK(c, launch_ke_partial(c->d, c->stream));
+    HIPCHK(c, launch_rep_reduce(c->d, 1, c->stream));
+    HIPCHK(c, launch_store_obs(c->d, c->obs_stage, c->stream));
+    std::vector<double> ke(4 * nr), pw(4 * nr);
+    HIPCHK(c, hipMemcpyAsync(ke.data(), c->obs_stage, 32 * nr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    TRY(forces(c, true));
+    HIPCHK(c, launch_rep_reduce(c->d, 6, c->stream));
+    HIPCHK(c, launch_store_obs(c->d, c->obs_stage, c->stream));
+    HIPCHK(c, hipMemcpyAsync(pw.data(), c->obs_stage, 32 * nr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t r = 0; r < nr; ++r) {
+        const double KE = 0.5 * ke[4 * r + 0];
+        const double PE = pw[4 * r + 1], W = pw[4 * r + 2];
+        const double n = c->reps[r].n, L = c->reps[r].box, V = L * L * L;
+        const double T = 2.0 * KE / (3.0 * n);
+        host_out[6 * r + 0] = KE;
+        host_out[6 * r + 1] = PE;
+        host_out[6 * r + 2] = W;
+        host_out[6 * r + 3] = T;
+        host_out[6 * r + 4] = KE + PE;
+        host_out[6 * r + 5] = n * T / V + W / (3.0 * V);
+    }
+    return KAMD_OK;
+}
+
+extern "C" int md_thermostat_state(kamd_ctx *c, double *host_out)
+{
+    if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");
+    std::vector<RepDyn> dyn(c->reps.size());
+    HIPCHK(c, hipMemcpyAsync(dyn.data(), c->d.dyn, sizeof(RepDyn) * dyn.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t r = 0; r < dyn.size(); ++r) {
+        host_out[2 * r] = dyn[r].xi;
+        host_out[2 * r + 1] = dyn[r].lns;
+    }
+    return KAMD_OK;
+}
+
+extern "C" int md_sync(kamd_ctx *c)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    return do_export(c);
+}
+
+extern "C" int md_import(kamd_ctx *c)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (!c->st.x || !c->st.y || !c->st.z || !c->st.vx || !c->st.vy || !c->st.vz)
+        return fail(c, KAMD_EINVAL, "the caller arrays x..vz were not given at md_init");
+    const double *a[9] = {c->st.x, c->st.y, c->st.z, c->st.vx, c->st.vy, c->st.vz, nullptr, nullptr, nullptr};
+    HIPCHK(c, launch_import(c->d, a, c->st.img, c->stream));
+    TRY(force_rebuild_all(c));
+    TRY(forces(c, false));
+    return maybe_export(c);
+}
+
+extern "C" int md_graph_capture(kamd_ctx *c, int32_t nsteps, int32_t ensemble, int32_t mode, int32_t n_reassign,
+                                double tau)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (nsteps <= 0) return fail(c, KAMD_EINVAL, "nsteps must be > 0");
+    if (ensemble == 1) {
+        if (mode == KAMD_NVT_STOCHASTIC) {
+            if (n_reassign <= 0 || nsteps % n_reassign) return fail(c, KAMD_EINVAL, "captured stochastic steps need nsteps %% n_reassign == 0");
+            if (c->step % n_reassign) return fail(c, KAMD_EINVAL, "capture the stochastic bath at a step count divisible by n_reassign");
+        } else if (mode == KAMD_NVT_NOSE_HOOVER) {
+            if (!(tau > 0.0)) return fail(c, KAMD_EINVAL, "tau must be > 0");
+            TRY(set_Q(c, tau));
+        } else {
+            return fail(c, KAMD_EINVAL, "bad thermostat mode");
+        }
+    } else if (ensemble != 0) {
+        return fail(c, KAMD_EINVAL, "ensemble must be 0 (NVE) or 1 (NVT)");
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);
+    // the device step counter drives the draw tags inside the graph
+    int32_t host_step = (int32_t)c->step;
+    HIPCHK(c, hipMemcpy(c->d.counters + 1, &host_step, 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    int r = enqueue_steps(c, nsteps, ensemble, mode, n_reassign, true);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (r) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return fail(c, KAMD_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    c->graph = g;
+    HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+    c->graph_steps = nsteps;
+    return KAMD_OK;
+}
+
+extern "C" int md_graph_launch(kamd_ctx *c)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (!c->graph_exec) return fail(c, KAMD_ESTATE, "no graph captured");
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+    c->step += c->graph_steps;
+    return maybe_export(c);
+}
+
+extern "C" int md_set_list_params(kamd_ctx *c, double skin, int32_t cell_div)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    return apply_list_params(c, skin, cell_div, false);
+}
+
+extern "C" int md_stats(kamd_ctx *c, double *host_out)
+{
+    if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");
+    int32_t cnt[8];
+    HIPCHK(c, hipMemcpyAsync(cnt, c->d.counters, 32, hipMemcpyDeviceToHost, c->stream));
+    std::vector<int32_t> nlen(c->d.npad_total), id(c->d.npad_total);
+    HIPCHK(c, hipMemcpyAsync(nlen.data(), c->d.nlen, 4 * nlen.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(id.data(), c->d.id, 4 * id.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double sum = 0.0, mx = 0.0;
+    int64_t cntr = 0;
+    for (size_t i = 0; i < nlen.size(); ++i)
+        if (id[i] >= 0) { sum += nlen[i]; mx = std::max(mx, (double)nlen[i]); ++cntr; }
+    host_out[0] = (double)c->step;
+    host_out[1] = (double)cnt[0];
+    host_out[2] = (double)c->d.n_total;
+    host_out[3] = (double)c->d.rows;
+    host_out[4] = cntr ? sum / cntr : 0.0;
+    host_out[5] = mx;
+    host_out[6] = c->skin;
+    host_out[7] = (double)c->cell_div;
+    return KAMD_OK;
+}
+
+// ------------------------------------------------------------- checkpoints
+struct BlobHeader {
+    uint64_t magic;
+    int64_t n_total;
+    int64_t n_rep;
+    int64_t step;
+};
+static const uint64_t BLOB_MAGIC = 0x4b414d4453544131ull;
+
+static size_t blob_size(const kamd_ctx *c)
+{
+    const size_t nt = c->d.n_total;
+    return sizeof(BlobHeader) + 9 * 8 * nt + 3 * 4 * nt + sizeof(RepDyn) * c->reps.size();
+}
+
+static int ensure_tmp(kamd_ctx *c)
+{
+    if (!c->state_tmp) {
+        TRY(dalloc(c, &c->state_tmp, 9 * (size_t)c->d.n_total));
+        TRY(dalloc(c, &c->img_tmp, 3 * (size_t)c->d.n_total));
+    }
+    return KAMD_OK;
+}
+
+extern "C" int md_get_state(kamd_ctx *c, void *blob, size_t *bytes)
+{
+    if (!c || !bytes) return fail(c, KAMD_EINVAL, "null argument");
+    const size_t need = blob_size(c);
+    if (!blob) { *bytes = need; return KAMD_OK; }
+    if (*bytes < need) return fail(c, KAMD_EINVAL, "blob too small (%zu < %zu)", *bytes, need);
+    TRY(ensure_tmp(c));
+    const size_t nt = c->d.n_total;
+    double *a[9];
+    for (int k = 0; k < 9; ++k) a[k] = c->state_tmp + k * nt;
+    HIPCHK(c, launch_export(c->d, a, c->img_tmp, c->stream));
+    char *p = (char *)blob;
+    BlobHeader h{BLOB_MAGIC, (int64_t)nt, (int64_t)c->reps.size(), c->step};
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    HIPCHK(c, hipMemcpyAsync(p, c->state_tmp, 9 * 8 * nt, hipMemcpyDeviceToHost, c->stream));
+    p += 9 * 8 * nt;
+    HIPCHK(c, hipMemcpyAsync(p, c->img_tmp, 3 * 4 * nt, hipMemcpyDeviceToHost, c->stream));
+    p += 3 * 4 * nt;
+    HIPCHK(c, hipMemcpyAsync(p, c->d.dyn, sizeof(RepDyn) * c->reps.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *bytes = need;
+    return KAMD_OK;
+}
+
+extern "C" int md_set_state(kamd_ctx *c, const void *blob, size_t bytes)
+{
+    if (!c || !blob) return fail(c, KAMD_EINVAL, "null argument");
+    if (bytes < blob_size(c)) return fail(c, KAMD_EINVAL, "blob too small");
+    BlobHeader h;
+    std::memcpy(&h, blob, sizeof h);
+    if (h.magic != BLOB_MAGIC || h.n_total != c->d.n_total || h.n_rep != (int64_t)c->reps.size())
+        return fail(c, KAMD_EINVAL, "blob does not match this context");
+    TRY(ensure_tmp(c));
+    const size_t nt = c->d.n_total;
+    const char *p = (const char *)blob + sizeof h;
+    HIPCHK(c, hipMemcpyAsync(c->state_tmp, p, 9 * 8 * nt, hipMemcpyHostToDevice, c->stream));
+    p += 9 * 8 * nt;
+    HIPCHK(c, hipMemcpyAsync(c->img_tmp, p, 3 * 4 * nt, hipMemcpyHostToDevice, c->stream));
+    p += 3 * 4 * nt;
+    HIPCHK(c, hipMemcpyAsync(c->d.dyn, p, sizeof(RepDyn) * c->reps.size(), hipMemcpyHostToDevice, c->stream));
+    const double *a[9];
+    for (int k = 0; k < 9; ++k) a[k] = c->state_tmp + k * nt;
+    HIPCHK(c, launch_import(c->d, a, c->img_tmp, c->stream));
+    c->step = h.step;
+    int32_t host_step = (int32_t)c->step;
+    HIPCHK(c, hipMemcpyAsync(c->d.counters + 1, &host_step, 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    TRY(force_rebuild_all(c));
+    TRY(rebuild_chain(c));
+    return maybe_export(c);
+}
+
+extern "C" int md_autotune(kamd_ctx *c, int32_t probe_steps, double *host_out)
+{
+    if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");
+    if (probe_steps <= 0) return fail(c, KAMD_EINVAL, "probe_steps must be > 0");
+    size_t nb = 0;
+    TRY(md_get_state(c, nullptr, &nb));
+    std::vector<char> blob(nb);
+    TRY(md_get_state(c, blob.data(), &nb));
+    const double skin0 = c->skin;
+    const int div0 = c->cell_div;
+    const int64_t step0 = c->step;
+    double Lmin = 1e300;
+    for (auto &k : c->reps) Lmin = std::min(Lmin, k.box);
+    std::vector<double> skins;
+    for (double s : {0.2, 0.25, 0.3, 0.35, 0.4, 0.5})
+        if (c->rc_max + s < 0.5 * Lmin || s <= 0.2) skins.push_back(s);
+    double best_t = 1e300, best_s = skin0;
+    int best_d = div0;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    const int saved_sync = c->cfg.auto_sync;
+    c->cfg.auto_sync = 0;
+    int rc = KAMD_OK;
+    for (double s : skins) {
+        for (int dv = 1; dv <= 2 && !rc; ++dv) {
+            rc = apply_list_params(c, s, dv, false);
+            if (!rc) rc = md_set_state(c, blob.data(), nb);
+            if (!rc) rc = enqueue_steps(c, std::max(1, probe_steps / 4), 0, 0, 0, false);  // warm-up
+            if (rc) break;
+            if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(c, KAMD_EHIP, "event record"); break; }
+            rc = enqueue_steps(c, probe_steps, 0, 0, 0, false);
+            if (rc) break;
+            (void)hipEventRecord(e1, c->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            uint32_t word = 0;
+            (void)hipMemcpy(&word, c->d.err, 4, hipMemcpyDeviceToHost);
+            if (word == 0 && ms / probe_steps < best_t) {
+                best_t = ms / probe_steps;
+                best_s = s;
+                best_d = dv;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->cfg.auto_sync = saved_sync;
+    int rc2 = apply_list_params(c, best_s, best_d, false);
+    if (!rc2) rc2 = md_set_state(c, blob.data(), nb);
+    c->step = step0;
+    if (rc) return rc;
+    if (rc2) return rc2;
+    host_out[0] = best_s;
+    host_out[1] = best_d;
+    host_out[2] = best_t;
+    return KAMD_OK;
+}
+
+extern "C" int md_profile(kamd_ctx *c, int32_t nsteps, double *host_out)
+{
+    if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");
+    if (nsteps <= 0) return fail(c, KAMD_EINVAL, "nsteps must be > 0");
+    const Dev &d = c->d;
+    const double dt = c->cfg.dt;
+    std::vector<hipEvent_t> ev(6 * (size_t)nsteps + 2);
+    for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
+    int32_t cnt0[8], cnt1[8];
+    HIPCHK(c, hipMemcpyAsync(cnt0, d.counters, 32, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    size_t k = 0;
+    HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+    int rc = KAMD_OK;
+    for (int s = 1; s <= nsteps && !rc; ++s) {
+        // streaming pass before the forces (drift, or kick of the previous step + drift)
+        HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+        if (s == 1) HIPCHK(c, launch_drift(d, dt, c->stream));
+        else HIPCHK(c, launch_kick_drift(d, dt, false, c->stream));
+        HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+        rc = rebuild_chain(c);
+        HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+        HIPCHK(c, launch_force(d, c->model, c->cfg.precision, false, true, c->stream));
+        HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+        if (s == nsteps) {
+            HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+            HIPCHK(c, launch_kick_nve(d, dt, false, c->stream));
+            HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+        }
+    }
+    HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+    HIPCHK(c, hipEventSynchronize(ev[k - 1]));
+    double tf = 0.0, ts = 0.0, tr = 0.0;
+    float ms = 0.0f;
+    size_t q = 1;
+    for (int s = 1; s <= nsteps; ++s) {
+        HIPCHK(c, hipEventElapsedTime(&ms, ev[q], ev[q + 1])); ts += ms;
+        HIPCHK(c, hipEventElapsedTime(&ms, ev[q + 1], ev[q + 2])); tr += ms;
+        HIPCHK(c, hipEventElapsedTime(&ms, ev[q + 2], ev[q + 3])); tf += ms;
+        q += 4;
+        if (s == nsteps) {
+            HIPCHK(c, hipEventElapsedTime(&ms, ev[q], ev[q + 1])); ts += ms;
+            q += 2;
+        }
+    }
+    HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[k - 1]));
+    const double total = ms;
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    c->step += nsteps;
+    HIPCHK(c, hipMemcpyAsync(cnt1, d.counters, 32, hipMemcpyDeviceToHost, c->stream));
+    // in-cutoff ordered pairs of the final configuration
+    TRY(forces(c, true));
+    HIPCHK(c, launch_rep_reduce(d, 8, c->stream));
+    HIPCHK(c, launch_store_obs(d, c->obs_stage, c->stream));
+    std::vector<double> o(4 * c->reps.size());
+    HIPCHK(c, hipMemcpyAsync(o.data(), c->obs_stage, 8 * o.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double pairs = 0.0;
+    for (size_t r = 0; r < c->reps.size(); ++r) pairs += o[4 * r + 3];
+    host_out[0] = tf / nsteps;
+    host_out[1] = ts / nsteps;
+    host_out[2] = total;
+    host_out[3] = (double)(cnt1[0] - cnt0[0]);
+    host_out[4] = pairs;
+    host_out[5] = nsteps;
+    host_out[6] = tr / nsteps;
+    host_out[7] = 0.0;
+    return maybe_export(c);
+}
+
+extern "C" int md_status(kamd_ctx *c, uint32_t *word)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    uint32_t w = 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&w, c->d.err, 4, hipMemcpyDeviceToHost));
+    if (word) *word = w;
+    if (w) return fail(c, KAMD_EDEVICE, "device error word 0x%x", w);
+    return KAMD_OK;
+}
+
+extern "C" int md_destroy(kamd_ctx *c)
+{
+    if (!c) return KAMD_OK;
+    (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
+    for (void *p : c->allocs) (void)hipFree(p);
+    c->allocs.clear();
+    delete c;
+    return KAMD_OK;
+}

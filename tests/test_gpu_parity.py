@@ -1,0 +1,373 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 CPU oracle.
+
+Inputs are seeded synthetic Kob-Andersen liquids (jittered lattice relaxed by
+the oracle's own stochastic-bath run) fed identically to both sides.
+Tolerances: forces normwise 1e-12 (FP64) / 1e-5 (mixed);
+RDF counts bit-exact; MSD and thermostat draws 1e-12; short trajectories
+within the rounding growth of a few tens of steps.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2001_07089_amd import md
+from paper_2001_07089_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+_CACHE = {}
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def relaxed(n, T=1.0, seed=1, rho=1.2):
+    """Oracle-relaxed liquid: (x, y, z, vx, vy, vz, n_a, L)."""
+    key = (n, T, seed, rho)
+    if key not in _CACHE:
+        L = W.box_for(n, rho)
+        na = W.n_a_for(n)
+        x, y, z = W.lattice_config(n, L, seed, 0.08)
+        vx, vy, vz = W.gaussian_velocities(n, math.sqrt(T), seed + 1)
+        st = O.State(x, y, z, vx, vy, vz, na, L)
+        st.compute_forces()
+        O.run(st, 0.001, 150, nb=5, T=T, seed=seed)
+        O.run(st, 0.003, 150, nb=10, T=T, seed=seed, step0=150)
+        _CACHE[key] = (st.x.copy(), st.y.copy(), st.z.copy(), st.vx.copy(), st.vy.copy(), st.vz.copy(), na, L)
+    return _CACHE[key]
+
+
+def system(configs, precision="fp64", **kw):
+    """configs: list of (n, T, seed, rho) relaxed liquids batched in one context."""
+    reps, pos, vel = [], [[], [], []], [[], [], []]
+    for i, (n, T, seed, rho) in enumerate(configs):
+        x, y, z, vx, vy, vz, na, L = relaxed(n, T, seed, rho)
+        reps.append((n, na, L, T, 1000 + seed))
+        for k, a in enumerate((x, y, z)):
+            pos[k].append(a)
+        for k, a in enumerate((vx, vy, vz)):
+            vel[k].append(a)
+    pos = [np.concatenate(p) for p in pos]
+    vel = [np.concatenate(v) for v in vel]
+    return md.System(reps, precision=precision, positions=pos, velocities=vel, **kw)
+
+
+def normwise(a, b):
+    num = sum(np.sum((a[k] - b[k]) ** 2) for k in range(3))
+    den = sum(np.sum(b[k] ** 2) for k in range(3))
+    return math.sqrt(num / den)
+
+
+@pytest.mark.parametrize("n", [500, 2000, 4000])
+def test_forces_fp64_match_oracle(n):
+    log(f"case forces fp64 n={n}")
+    s = system([(n, 1.0, 3, 1.2)], "fp64")
+    obs = s.forces(energy=True)
+    a = s.numpy()
+    x, y, z, _, _, _, na, L = relaxed(n, 1.0, 3)
+    fx, fy, fz, pe, w = O.forces(x, y, z, na, L, "brute")
+    err = normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz))
+    log(f"  normwise {err:.3e}")
+    assert err <= 1e-12
+    assert obs[0, 0] == pytest.approx(pe, rel=1e-12)
+    assert obs[0, 1] == pytest.approx(w, rel=1e-12)
+    assert s.status() == 0
+    s.close()
+
+
+@pytest.mark.parametrize("n,skin,cell_div", [(500, 0.2, 1), (500, 0.4, 2), (2000, 0.5, 1), (4000, 0.25, 2),
+                                             (1200, 0.0, 1)])
+def test_forces_list_parameters(n, skin, cell_div):
+    """Pair sets of every list geometry (pruned and unpruned stencils, 1-5
+    cells per edge, zero skin) against the O(N^2) oracle."""
+    log(f"case list n={n} skin={skin} cell_div={cell_div}")
+    for prec, tol in (("fp64", 1e-12), ("mixed_fixed", 1e-5)):
+        s = system([(n, 1.0, 25, 1.2)], prec, skin=skin, cell_div=cell_div)
+        a = s.numpy()
+        x, y, z, _, _, _, na, L = relaxed(n, 1.0, 25)
+        fx, fy, fz, _, _ = O.forces(x, y, z, na, L, "brute")
+        err = normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz))
+        assert err <= tol, (prec, err)
+        s.step_nve(100)
+        assert s.status() == 0
+        s.close()
+
+
+@pytest.mark.parametrize("prec", ["mixed", "mixed_fixed"])
+@pytest.mark.parametrize("n,T", [(2000, 1.0), (4000, 0.5)])
+def test_forces_mixed_match_oracle(prec, n, T):
+    log(f"case forces {prec} n={n} T={T}")
+    s = system([(n, T, 4, 1.2)], prec)
+    obs = s.forces(energy=True)
+    a = s.numpy()
+    x, y, z, _, _, _, na, L = relaxed(n, T, 4)
+    fx, fy, fz, pe, w = O.forces(x, y, z, na, L, "cell")
+    err = normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz))
+    frms = math.sqrt(np.mean(fx ** 2 + fy ** 2 + fz ** 2))
+    mx = max(np.max(np.abs(a["ax"] - fx)), np.max(np.abs(a["ay"] - fy)), np.max(np.abs(a["az"] - fz)))
+    log(f"  normwise {err:.3e}  max|dF|/Frms {mx / frms:.3e}  PE rel {(obs[0, 0] - pe) / abs(pe):.3e}")
+    assert err <= 1e-5
+    assert obs[0, 0] == pytest.approx(pe, rel=1e-5)
+    assert obs[0, 1] == pytest.approx(w, rel=1e-5)
+    assert s.status() == 0
+    s.close()
+
+
+def test_fixed_point_sum_of_forces_is_exactly_zero():
+    log("case fixed newton")
+    s = system([(4000, 1.0, 5, 1.2), (1500, 0.8, 6, 1.2)], "mixed_fixed")
+    a = s.numpy()
+    for r in range(2):
+        sl = s.replica_slice(r)
+        for k in ("ax", "ay", "az"):
+            q = np.rint(a[k][sl] * 2.0 ** 26).astype(np.int64)
+            assert np.array_equal(q.astype(np.float64) / 2.0 ** 26, a[k][sl])
+            assert int(q.sum()) == 0
+    s.close()
+
+
+def test_batched_replicas_match_oracle_per_replica():
+    cfgs = [(500, 1.0, 7, 1.2), (3000, 0.6, 8, 1.2), (1200, 1.5, 9, 1.1), (2500, 0.8, 10, 1.3)]
+    log("case batched forces", cfgs)
+    for prec, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+        s = system(cfgs, prec)
+        obs = s.forces(energy=True)
+        a = s.numpy()
+        for r, (n, T, seed, rho) in enumerate(cfgs):
+            x, y, z, _, _, _, na, L = relaxed(n, T, seed, rho)
+            fx, fy, fz, pe, w = O.forces(x, y, z, na, L, "brute")
+            sl = s.replica_slice(r)
+            err = normwise((a["ax"][sl], a["ay"][sl], a["az"][sl]), (fx, fy, fz))
+            assert err <= tol, (prec, r, err)
+            assert obs[r, 0] == pytest.approx(pe, rel=tol)
+        s.close()
+
+
+def test_nve_fp64_trajectory_matches_oracle():
+    n, T = 2000, 1.0
+    log("case nve fp64 trajectory")
+    s = system([(n, T, 11, 1.2)], "fp64")
+    x, y, z, vx, vy, vz, na, L = relaxed(n, T, 11)
+    st = O.State(x, y, z, vx, vy, vz, na, L)
+    st.compute_forces()
+    nsteps = 30
+    O.run(st, 0.005, nsteps)
+    s.step_nve(nsteps)
+    a = s.numpy()
+    img = s.images()
+    ux = a["x"] + img[0] * L
+    ox = st.x + st.img[0] * L
+    assert np.max(np.abs(ux - ox)) < 1e-9
+    assert np.max(np.abs(a["vx"] - st.vx)) < 1e-8
+    assert np.array_equal(img, st.img)
+    assert s.status() == 0
+    s.close()
+
+
+@pytest.mark.parametrize("n,dr_mode", [(1000, "paper"), (4000, "halfbox200"), (3000, "short")])
+def test_rdf_counts_bit_exact(n, dr_mode):
+    log(f"case rdf n={n} {dr_mode}")
+    rho = 1.2
+    if dr_mode == "paper":  # N = 1000, L = 9.4, dr = 0.1, n_bins = int(L/2/dr) (Sec. VI.A.1)
+        L = 9.4
+        rho = n / L ** 3
+        dr, nb = 0.1, int(L / 2 / 0.1)
+    x, y, z, _, _, _, na, L = relaxed(n, 1.0, 12, rho)
+    if dr_mode == "halfbox200":
+        dr, nb = (L / 2) / 200, 200
+    elif dr_mode == "short":
+        dr, nb = 0.02, 150
+    s = system([(n, 1.0, 12, rho)], "fp64")
+    h = s._host(s.rdf(dr, nb)).astype(np.uint64)[0]
+    ref = O.rdf_hist(x, y, z, na, L, dr, nb)
+    assert np.array_equal(h, ref), np.argwhere(h != ref)[:5]
+    s.close()
+
+
+def test_msd_matches_oracle():
+    n, T = 2000, 1.0
+    log("case msd")
+    s = system([(n, T, 13, 1.2)], "fp64")
+    x, y, z, _, _, _, na, L = relaxed(n, T, 13)
+    s.msd_set_origin(2)
+    s.step_nve(200)
+    got = s.msd(2)[0]
+    a = s.numpy()
+    img = s.images()
+    ref = O.msd(a["x"], a["y"], a["z"], img, na, L, x, y, z)
+    assert got == pytest.approx(ref, rel=1e-12)
+    assert got[1] > got[0] > 0  # smaller B particles move further
+    s.close()
+
+
+def test_stochastic_bath_draws_match_oracle():
+    n, T = 1500, 0.2
+    log("case stochastic bath draw")
+    s = system([(n, T, 14, 1.2)], "fp64")
+    seed = 1000 + 14
+    s.step_nvt(10, md.NVT_STOCHASTIC, n_reassign=10)
+    a = s.numpy()
+    # replica 0, draw tag = step 10, ids = caller index within the replica
+    vx, vy, vz = O.mb_velocities(n, T, seed, rep=0, tag=10)
+    assert np.max(np.abs(a["vx"] - vx)) < 1e-12
+    assert np.max(np.abs(a["vz"] - vz)) < 1e-12
+    ke = 0.5 * np.sum(a["vx"] ** 2 + a["vy"] ** 2 + a["vz"] ** 2)
+    assert 2 * ke / (3 * n) == pytest.approx(T, rel=1e-13)
+    s.close()
+
+
+def test_nose_hoover_matches_oracle():
+    n, T0, T = 1500, 1.0, 0.7
+    tau = 0.5
+    log("case nose-hoover")
+    s = system([(n, T0, 15, 1.2)], "fp64")
+    x, y, z, vx, vy, vz, na, L = relaxed(n, T0, 15)
+    # the bath temperature is the replica temperature: rebuild with T = 0.7
+    s.close()
+    s = md.System([(n, na, L, T, 1)], precision="fp64", positions=(x, y, z), velocities=(vx, vy, vz))
+    st = O.State(x, y, z, vx, vy, vz, na, L)
+    st.compute_forces()
+    Q = 3 * n * T * tau ** 2
+    e = O.run_nh(st, 0.005, 20, T, Q)
+    s.step_nvt(20, md.NVT_NOSE_HOOVER, tau=tau)
+    a = s.numpy()
+    th = md.md_thermostat_state(s.ctx, 1)[0]
+    img = s.images()
+    assert np.max(np.abs(a["x"] + img[0] * L - (st.x + st.img[0] * L))) < 1e-9
+    assert th[0] == pytest.approx(st.xi, rel=1e-9, abs=1e-12)
+    assert th[1] == pytest.approx(st.lns, rel=1e-9, abs=1e-12)
+    assert e[-1, 3] == pytest.approx(st.xi)
+    s.close()
+
+
+def _state_equal(a, b):
+    return all(np.array_equal(a[k], b[k]) for k in a)
+
+
+def test_graph_replay_equals_eager_fixed():
+    log("case graph replay")
+    cfg = [(3000, 0.8, 16, 1.2)]
+    s1 = system(cfg, "mixed_fixed")
+    s2 = system(cfg, "mixed_fixed")
+    md.md_graph_capture(s2.ctx, 50, 0)
+    for _ in range(3):
+        s1.step_nve(50)
+        md.md_graph_launch(s2.ctx)
+        s2.sync()
+        assert _state_equal(s1.numpy(), s2.numpy())
+    assert s1.status() == 0 and s2.status() == 0
+    s1.close()
+    s2.close()
+
+
+def test_graph_replay_stochastic_bath():
+    log("case graph stochastic")
+    cfg = [(1500, 0.5, 17, 1.2)]
+    s1 = system(cfg, "mixed_fixed")
+    s2 = system(cfg, "mixed_fixed")
+    md.md_graph_capture(s2.ctx, 20, 1, md.NVT_STOCHASTIC, 10)
+    for _ in range(2):
+        s1.step_nvt(20, md.NVT_STOCHASTIC, 10)
+        md.md_graph_launch(s2.ctx)
+        s2.sync()
+        a, b = s1.numpy(), s2.numpy()
+        assert np.max(np.abs(a["vx"] - b["vx"])) < 1e-12
+        assert np.max(np.abs(a["x"] - b["x"])) < 1e-12
+    s1.close()
+    s2.close()
+
+
+def test_replica_in_batch_equals_alone_fixed():
+    log("case batch invariance")
+    a_cfg = (2000, 0.9, 18, 1.2)
+    batch = [(800, 1.2, 19, 1.2), a_cfg, (3500, 0.6, 20, 1.2)]
+    sb = system(batch, "mixed_fixed")
+    sa = system([a_cfg], "mixed_fixed")
+    sb.step_nve(150)
+    sa.step_nve(150)
+    ab, aa = sb.numpy(), sa.numpy()
+    sl = sb.replica_slice(1)
+    for k in aa:
+        assert np.array_equal(ab[k][sl], aa[k]), k
+    sb.close()
+    sa.close()
+
+
+def test_checkpoint_resume_is_bitwise_fixed():
+    log("case checkpoint")
+    cfg = [(2500, 0.8, 21, 1.2)]
+    s1 = system(cfg, "mixed_fixed")
+    s1.step_nve(120)
+    ref = s1.numpy()
+    s2 = system(cfg, "mixed_fixed")
+    s2.step_nve(60)
+    blob = md.md_get_state(s2.ctx)
+    s3 = system(cfg, "mixed_fixed")
+    md.md_set_state(s3.ctx, blob)
+    s3.step_nve(60)
+    assert _state_equal(ref, s3.numpy())
+    for s in (s1, s2, s3):
+        s.close()
+
+
+def test_list_overflow_sets_error_bit():
+    log("case list overflow")
+    s = system([(1000, 1.0, 22, 1.2)], "fp64", list_capacity=0.05)
+    w = s.status()
+    assert w & md.DEV_LIST_OVERFLOW
+    s.close()
+
+
+def test_rsa_init_and_mb_velocities():
+    n = 4000
+    log("case rsa init")
+    L = W.box_for(n, 1.2)
+    s = md.System([(n, W.n_a_for(n), L, 2.0, 77)], precision="fp64", init="rsa", min_dist=0.8)
+    a = s.numpy()
+    assert O.min_distance(a["x"], a["y"], a["z"], L) >= 0.8 - 1e-12
+    assert np.all(a["x"] >= 0) and np.all(a["x"] < L)
+    for k in ("vx", "vy", "vz"):
+        assert abs(a[k].sum()) < 1e-10
+    ke = 0.5 * np.sum(a["vx"] ** 2 + a["vy"] ** 2 + a["vz"] ** 2)
+    assert 2 * ke / (3 * n) == pytest.approx(2.0, rel=1e-13)
+    # initial forces are those of the positions
+    fx, fy, fz, _, _ = O.forces(a["x"], a["y"], a["z"], W.n_a_for(n), L, "cell")
+    assert normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz)) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed", "mixed_fixed"])
+def test_nve_energy_drift(prec):
+    n, T = 4000, 0.5
+    log(f"case drift {prec}")
+    s = system([(n, T, 23, 1.2)], prec)
+    s.step_nvt(500, md.NVT_STOCHASTIC, 50)
+    s.step_nve(200)
+    e0 = s.observables()[0, 4]
+    es = []
+    for _ in range(10):
+        s.step_nve(200)
+        es.append(s.observables()[0, 4])
+    drift = abs(es[-1] - e0) / abs(e0)
+    log(f"  E0={e0:.6f} drift over 2000 steps {drift:.2e}")
+    assert drift < 1e-4
+    assert s.status() == 0
+    s.close()
+
+
+def test_autotune_picks_a_valid_skin():
+    log("case autotune")
+    s = system([(4000, 0.8, 24, 1.2)], "mixed")
+    x0 = s.numpy()["x"].copy()
+    res = md.md_autotune(s.ctx, 20)
+    assert 0.2 <= res["skin"] <= 0.5 and res["cell_div"] in (1, 2) and res["ms_per_step"] > 0
+    s.sync()
+    assert np.array_equal(s.numpy()["x"], x0)  # state restored
+    s.step_nve(50)
+    assert s.status() == 0
+    s.close()
