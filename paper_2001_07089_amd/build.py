@@ -38,7 +38,7 @@ def hipcc() -> str:
 def common_flags():
     return ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-            "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-result"]
+            "-I", INCLUDE, "-I", CSRC, "-pthread", "-Wall", "-Wno-unused-result"]
 
 
 def _compile(src, extra):
@@ -64,7 +64,7 @@ def build(verbose: bool = False) -> str:
             if verbose and log.strip():
                 print(log, file=sys.stderr)
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
+    cmd = [hipcc(), "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

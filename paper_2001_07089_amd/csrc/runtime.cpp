@@ -12,6 +12,7 @@
 #include <cstring>
 #include <random>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace kamd;
@@ -662,7 +663,8 @@ extern "C" int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replic
             HIPCHK(c, launch_import(c->d, a, st->img, c->stream));
         } else {
             std::vector<double> hx(nt), hy(nt), hz(nt);
-            for (int q = 0; q < n_rep; ++q) {
+            // replicas are independent: place them on host threads
+            auto place = [&](int q) {
                 const kamd_replica &K = c->reps[q];
                 std::vector<double> x, y, z;
                 bool ok = false;
@@ -671,7 +673,14 @@ extern "C" int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replic
                 std::copy(x.begin(), x.end(), hx.begin() + K.offset);
                 std::copy(y.begin(), y.end(), hy.begin() + K.offset);
                 std::copy(z.begin(), z.end(), hz.begin() + K.offset);
-            }
+            };
+            const int nthr = std::max(1, std::min<int>(n_rep, (int)std::thread::hardware_concurrency()));
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nthr; ++t)
+                pool.emplace_back([&, t]() {
+                    for (int q = t; q < n_rep; q += nthr) place(q);
+                });
+            for (auto &th : pool) th.join();
             double *tmp;
             TRY(dalloc(c, &tmp, 3 * (size_t)nt));
             HIPCHK(c, hipMemcpyAsync(tmp, hx.data(), 8 * nt, hipMemcpyHostToDevice, c->stream));

@@ -1,0 +1,154 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py
+times (single 2^20-particle system; 256-replica batch), on inputs from the
+seeded workload generator.  The oracle evaluates every force with its
+cell-list routine (OpenMP); the RDF at N = 32000 is compared bin by bin
+against the O(N^2) oracle; the MSD at 2^20 against a closed form.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2001_07089_amd import md
+from paper_2001_07089_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def normwise(a, b):
+    num = sum(np.sum((a[k] - b[k]) ** 2) for k in range(3))
+    den = sum(np.sum(b[k] ** 2) for k in range(3))
+    return math.sqrt(num / den)
+
+
+def _large_inputs():
+    wl = W.ka_large()
+    r = wl.replicas[0]
+    x, y, z = W.lattice_config(r.n, r.box, r.seed, 0.1)
+    vx, vy, vz = W.gaussian_velocities(r.n, math.sqrt(r.temperature), r.seed + 1)
+    return r, (x, y, z), (vx, vy, vz)
+
+
+@pytest.mark.parametrize("prec,tol", [("mixed_fixed", 1e-5), ("fp64", 1e-12)])
+def test_large_system_forces_match_oracle(prec, tol):
+    r, pos, vel = _large_inputs()
+    log(f"case large forces {prec} n={r.n}")
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision=prec, positions=pos,
+                  velocities=vel, skin=0.4)
+    a = s.numpy(("ax", "ay", "az"))
+    fx, fy, fz, pe, _ = O.forces(*pos, r.n_a, r.box, "cell")
+    err = normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz))
+    log(f"  normwise {err:.3e}")
+    assert err <= tol
+    obs = s.forces(energy=True)
+    assert obs[0, 0] == pytest.approx(pe, rel=max(tol, 1e-12))
+    assert s.status() == 0
+    s.close()
+
+
+def test_large_system_graph_steps_are_sound():
+    """The bench's timed configuration: graph-captured NVE steps at 2^20 particles
+    with fixed-point forces; forces after the steps match the oracle on the
+    resulting positions, the force sum is exactly zero, energy is conserved."""
+    r, pos, vel = _large_inputs()
+    log("case large graph")
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision="mixed_fixed", positions=pos,
+                  velocities=vel, skin=0.4, auto_sync=False)
+    s.step_nvt(300, md.NVT_STOCHASTIC, n_reassign=10)
+    e0 = s.observables()[0, 4]
+    md.md_graph_capture(s.ctx, 200, 0)
+    md.md_graph_launch(s.ctx)
+    e1 = s.observables()[0, 4]
+    assert s.status() == 0
+    assert abs(e1 - e0) / abs(e0) < 2e-4
+    s.sync()
+    a = s.numpy()
+    for k in ("ax", "ay", "az"):
+        q = np.rint(a[k] * 2.0 ** 26).astype(np.int64)
+        assert int(q.sum()) == 0
+    fx, fy, fz, _, _ = O.forces(a["x"], a["y"], a["z"], r.n_a, r.box, "cell")
+    assert normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz)) <= 1e-5
+    st = md.md_stats(s.ctx)
+    assert st["max_list_len"] <= st["list_rows"]
+    s.close()
+
+
+def test_batch_of_256_replicas_matches_oracle_per_replica():
+    wl = W.ka_batch_small()
+    log(f"case batch {len(wl.replicas)} replicas, {wl.n_total} particles")
+    reps, pos = [], [[], [], []]
+    for r in wl.replicas:
+        x, y, z = W.lattice_config(r.n, r.box, r.seed, 0.1)
+        for k, v in enumerate((x, y, z)):
+            pos[k].append(v)
+        reps.append((r.n, r.n_a, r.box, r.temperature, r.seed))
+    cat = [np.concatenate(p) for p in pos]
+    s = md.System(reps, precision="mixed", positions=cat, velocities=None, skin=0.3)
+    obs = s.forces(energy=True)
+    a = s.numpy(("ax", "ay", "az"))
+    worst = 0.0
+    for i, r in enumerate(wl.replicas):
+        sl = s.replica_slice(i)
+        fx, fy, fz, pe, _ = O.forces(pos[0][i], pos[1][i], pos[2][i], r.n_a, r.box, "cell")
+        err = normwise((a["ax"][sl], a["ay"][sl], a["az"][sl]), (fx, fy, fz))
+        worst = max(worst, err)
+        assert err <= 1e-5, (i, r.n, err)
+        assert obs[i, 0] == pytest.approx(pe, rel=1e-5)
+    log(f"  worst normwise {worst:.3e}")
+    assert s.status() == 0
+    s.close()
+
+
+def test_medium_rdf_200_bins_to_half_box_bit_exact():
+    wl = W.ka_medium()
+    r = wl.replicas[0]
+    log(f"case rdf n={r.n}")
+    x, y, z = W.lattice_config(r.n, r.box, r.seed, 0.25)
+    dr = (r.box / 2) / 200
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision="fp64", positions=(x, y, z))
+    h = s._host(s.rdf(dr, 200)).astype(np.uint64)[0]
+    ref = O.rdf_hist(x, y, z, r.n_a, r.box, dr, 200)
+    assert np.array_equal(h, ref)
+    assert int(h.sum()) > 0
+    s.close()
+
+
+def test_large_msd_closed_form():
+    r, pos, vel = _large_inputs()
+    log("case large msd")
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision="mixed_fixed", positions=pos,
+                  velocities=vel, skin=0.4)
+    s.msd_set_origin(0)
+    # shift A particles by (0.7, -1.1, L + 0.2) and B particles by (-2.5, 0, 0):
+    # positions wrap, image counters record the crossings
+    L = r.box
+    shift = np.zeros((3, r.n))
+    shift[:, :r.n_a] = np.array([0.7, -1.1, L + 0.2])[:, None]
+    shift[:, r.n_a:] = np.array([-2.5, 0.0, 0.0])[:, None]
+    new = []
+    img = np.zeros((3, r.n), np.int32)
+    for k in range(3):
+        u = pos[k] + shift[k]
+        kk = np.floor(u / L)
+        u = u - kk * L
+        u[u >= L] = 0.0
+        img[k] = kk.astype(np.int32)
+        new.append(u)
+    with s.torch.cuda.stream(s.stream):
+        for k, key in enumerate(("x", "y", "z")):
+            s.t[key].copy_(s.torch.as_tensor(new[k]))
+        s.img.copy_(s.torch.as_tensor(img))
+    s.stream.synchronize()
+    md.md_import(s.ctx)
+    got = s.msd(0)[0]
+    exp_a = 0.7 ** 2 + 1.1 ** 2 + (L + 0.2) ** 2
+    assert got[0] == pytest.approx(exp_a, rel=1e-12)
+    assert got[1] == pytest.approx(6.25, rel=1e-12)
+    s.close()
