@@ -65,4 +65,96 @@ __device__ inline bool rebuild_flag(const Dev &d, int r)
     return d.rb_force[r] != 0 || (double)__uint_as_float(d.maxdisp[r]) > d.rep[r].disp_thr2;
 }
 
+// ------------------------------------------------ integration helpers
+__device__ inline double wrap_img(double u, double L, double invL, int32_t &img)
+{
+    double k = floor(u * invL);
+    u = fma(-k, L, u);
+    if (u >= L) { u -= L; k += 1.0; }
+    if (u < 0.0) { u += L; k -= 1.0; }
+    img += (int32_t)k;
+    return u;
+}
+
+// Position half of a velocity-Verlet step for slot s, from the velocity v at
+// the start of the step and the acceleration a: v_h = v + c (a - (xi + xi_a)
+// v), r += dt (v + dt/2 (a - xi v)), wrap into [0, L) counting images.
+// Stores r, v_h and the image counters, writes the new u32 mirror into
+// mirror_out and returns the squared displacement since the last list build
+// in d2.  NVE: xi = xi_a = 0, c = dt/2.
+__device__ inline void drift_core(const Dev &d, int s, const RepInfo &R, double dt, double xi, double xia,
+                                  double c, const double v[3], const double a[3], uint4 *mirror_out, float &d2)
+{
+    const int np = d.npad_total;
+    const double L = R.L, invL = R.invL;
+    double r[3] = {d.x[s], d.y[s], d.z[s]};
+    double vn[3];
+    int32_t im[3] = {d.img[s], d.img[np + s], d.img[2 * np + s]};
+    uint32_t q[3];
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double g = a[k] - xi * v[k];
+        r[k] = fma(dt, fma(0.5 * dt, g, v[k]), r[k]);
+        vn[k] = fma(c, a[k] - (xi + xia) * v[k], v[k]);
+        fin = fin && isfinite(r[k]) && isfinite(vn[k]);
+        r[k] = wrap_img(r[k], L, invL, im[k]);
+        q[k] = to_fix(r[k], invL);
+    }
+    d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
+    d.vx[s] = vn[0]; d.vy[s] = vn[1]; d.vz[s] = vn[2];
+    d.img[s] = im[0]; d.img[np + s] = im[1]; d.img[2 * np + s] = im[2];
+    mirror_out[s] = make_uint4(q[0], q[1], q[2], 0u);
+    const uint4 b = d.mbuild[s];
+    const float ex = (float)(int)(q[0] - b.x), ey = (float)(int)(q[1] - b.y),
+                ez = (float)(int)(q[2] - b.z);
+    const float h = (float)(R.L * 2.3283064365386963e-10);
+    d2 = (ex * ex + ey * ey + ez * ez) * (h * h);
+    if (!fin) set_err(d.err, KAMD_DEV_NONFINITE);
+}
+
+__device__ inline void drift_one(const Dev &d, int s, int rep, double dt, double xi, double xia,
+                                 double c, uint4 *mirror_out, float &d2)
+{
+    const double v[3] = {d.vx[s], d.vy[s], d.vz[s]};
+    const double a[3] = {d.ax[s], d.ay[s], d.az[s]};
+    drift_core(d, s, d.rep[rep], dt, xi, xia, c, v, a, mirror_out, d2);
+}
+
+// Per-replica maximum of the wavefront maxima of one block, one atomicMax per
+// replica present in the block (a block holds 4 consecutive wavefronts, which
+// may straddle two replicas).  All threads of the block must call it.
+__device__ inline void block_disp_max(uint32_t *maxdisp, bool valid, int rep, float d2)
+{
+    __shared__ float wmax[WAVES_PER_BLOCK];
+    __shared__ int wrep[WAVES_PER_BLOCK];
+    d2 = wave_max(d2);
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) {
+        wmax[wv] = d2;
+        wrep[wv] = valid ? rep : -1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // read first: the maximum only grows during the step, so most blocks
+        // find it already larger and skip the atomic
+        auto push = [&](int r, float m) {
+            const uint32_t bits = __float_as_uint(m);
+            const uint32_t cur = __hip_atomic_load(&maxdisp[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (bits > cur) atomicMax(&maxdisp[r], bits);
+        };
+        int r = -1;
+        float m = 0.0f;
+        for (int k = 0; k < WAVES_PER_BLOCK; ++k) {
+            if (wrep[k] != r) {
+                if (r >= 0) push(r, m);
+                r = wrep[k];
+                m = 0.0f;
+            }
+            m = fmaxf(m, wmax[k]);
+        }
+        if (r >= 0) push(r, m);
+    }
+}
+
 }  // namespace kamd

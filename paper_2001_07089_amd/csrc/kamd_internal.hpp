@@ -146,6 +146,10 @@ hipError_t launch_rb_list(const Dev &d, int cell_div, hipStream_t s);
 // The force kernel also closes the step's rebuild check (resets maxdisp and
 // rb_force) and, with step_inc, advances the device step counter.
 hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, bool step_inc, hipStream_t s);
+// Mixed precisions, NVE: forces fused with the closing half kick and the next
+// drift (new mirror into mirror_out, displacement maximum into md_out).
+hipError_t launch_force_kd(const Dev &d, const Model &m, int prec, double dt, uint4 *mirror_out, uint32_t *md_out,
+                           hipStream_t s);
 
 hipError_t launch_drift(const Dev &d, double dt, hipStream_t s);
 hipError_t launch_drift_nh(const Dev &d, double dt, hipStream_t s);

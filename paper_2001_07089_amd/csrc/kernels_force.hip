@@ -131,13 +131,23 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
     }
 }
 
-template <bool FIXED, bool ENERGY>
-__global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_inc)
+// KD (NVE steps only): after the force of slot s, close the step with the
+// half kick v += a dt/2 and open the next one (v += a dt/2, r += v dt, wrap,
+// new mirror into mirror_out, displacement into md_out) in the same pass.
+// Neighbours read their positions from d.mirror while mirror_out receives the
+// new ones, so the two must be different buffers; the forces are not stored.
+template <bool FIXED, bool ENERGY, bool KD>
+__global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_inc, double dt,
+                                                        uint4 *mirror_out, uint32_t *md_out)
 {
     close_step(d, step_inc);
     const int w = wave_id_remapped();
-    if (w >= d.nwaves) return;
+    const bool valid = w < d.nwaves;
+    float d2 = 0.0f;
+    int rep = -1;
+    if (valid) {
     const SegInfo &S = d.seg[d.wave_seg[w]];
+    rep = S.rep;
     const RepInfo &R = d.rep[S.rep];
     const int s = w * WAVE + lane_id();
     const uint4 mi = d.mirror[s];
@@ -214,10 +224,17 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
         const double lim = 1.0e8;
         if (fabs(fx) > lim || fabs(fy) > lim || fabs(fz) > lim) set_err(d.err, KAMD_DEV_FORCE_RANGE);
     }
-    d.ax[s] = fx;
-    d.ay[s] = fy;
-    d.az[s] = fz;
     if (!(isfinite(fx) && isfinite(fy) && isfinite(fz))) set_err(d.err, KAMD_DEV_NONFINITE);
+    if (!KD) {
+        d.ax[s] = fx;
+        d.ay[s] = fy;
+        d.az[s] = fz;
+    } else if ((s - S.slot0) < S.n) {
+        const double h = 0.5 * dt;
+        const double a[3] = {fx, fy, fz};
+        const double v[3] = {fma(h, fx, d.vx[s]), fma(h, fy, d.vy[s]), fma(h, fz, d.vz[s])};
+        drift_core(d, s, R, dt, 0.0, 0.0, h, v, a, mirror_out, d2);
+    }
     if (ENERGY) {
         pe = wave_sum(pe);
         vir = wave_sum(vir);
@@ -228,6 +245,8 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
             d.wred[4 * w + 3] = npair;
         }
     }
+    }
+    if (KD) block_disp_max(md_out, valid, rep, d2);
 }
 
 hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, bool step_inc, hipStream_t s)
@@ -238,12 +257,35 @@ hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, boo
         if (energy) hipLaunchKernelGGL(k_force_fp64<true>, dim3(nb), dim3(BLOCK), 0, s, d, m, si);
         else hipLaunchKernelGGL(k_force_fp64<false>, dim3(nb), dim3(BLOCK), 0, s, d, m, si);
     } else if (prec == 1) {
-        if (energy) hipLaunchKernelGGL((k_force_mixed<false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, si);
-        else hipLaunchKernelGGL((k_force_mixed<false, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si);
+        if (energy)
+            hipLaunchKernelGGL((k_force_mixed<false, true, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
+                               (uint4 *)nullptr, (uint32_t *)nullptr);
+        else
+            hipLaunchKernelGGL((k_force_mixed<false, false, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
+                               (uint4 *)nullptr, (uint32_t *)nullptr);
     } else {
-        if (energy) hipLaunchKernelGGL((k_force_mixed<true, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, si);
-        else hipLaunchKernelGGL((k_force_mixed<true, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si);
+        if (energy)
+            hipLaunchKernelGGL((k_force_mixed<true, true, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
+                               (uint4 *)nullptr, (uint32_t *)nullptr);
+        else
+            hipLaunchKernelGGL((k_force_mixed<true, false, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
+                               (uint4 *)nullptr, (uint32_t *)nullptr);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_force_kd(const Dev &d, const Model &m, int prec, double dt, uint4 *mirror_out, uint32_t *md_out,
+                           hipStream_t s)
+{
+    const int nb = (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    if (prec == 1)
+        hipLaunchKernelGGL((k_force_mixed<false, false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out,
+                           md_out);
+    else if (prec == 2)
+        hipLaunchKernelGGL((k_force_mixed<true, false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out,
+                           md_out);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

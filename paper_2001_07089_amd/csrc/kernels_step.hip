@@ -21,16 +21,6 @@
 
 namespace kamd {
 
-__device__ inline double wrap_img(double u, double L, double invL, int32_t &img)
-{
-    double k = floor(u * invL);
-    u = fma(-k, L, u);
-    if (u >= L) { u -= L; k += 1.0; }
-    if (u < 0.0) { u += L; k -= 1.0; }
-    img += (int32_t)k;
-    return u;
-}
-
 struct SlotCtx {
     int w, s;
     bool real;
@@ -51,77 +41,6 @@ __device__ inline bool slot_ctx(const Dev &d, SlotCtx &c)
     return true;
 }
 
-// Position half of the step (see file comment).  nh selects the friction
-// terms; otherwise xi = xi_a = 0 and c = dt/2.
-__device__ inline void drift_one(const Dev &d, int s, int rep, double dt, double xi, double xia,
-                                 double c, float &d2)
-{
-    const RepInfo &R = d.rep[rep];
-    const int np = d.npad_total;
-    const double L = R.L, invL = R.invL;
-    double v[3] = {d.vx[s], d.vy[s], d.vz[s]};
-    const double a[3] = {d.ax[s], d.ay[s], d.az[s]};
-    double r[3] = {d.x[s], d.y[s], d.z[s]};
-    int32_t im[3] = {d.img[s], d.img[np + s], d.img[2 * np + s]};
-    uint32_t q[3];
-    bool fin = true;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const double g = a[k] - xi * v[k];
-        r[k] = fma(dt, fma(0.5 * dt, g, v[k]), r[k]);
-        v[k] = fma(c, a[k] - (xi + xia) * v[k], v[k]);
-        fin = fin && isfinite(r[k]) && isfinite(v[k]);
-        r[k] = wrap_img(r[k], L, invL, im[k]);
-        q[k] = to_fix(r[k], invL);
-    }
-    d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
-    d.vx[s] = v[0]; d.vy[s] = v[1]; d.vz[s] = v[2];
-    d.img[s] = im[0]; d.img[np + s] = im[1]; d.img[2 * np + s] = im[2];
-    d.mirror[s] = make_uint4(q[0], q[1], q[2], 0u);
-    const uint4 b = d.mbuild[s];
-    const float ex = (float)(int)(q[0] - b.x), ey = (float)(int)(q[1] - b.y),
-                ez = (float)(int)(q[2] - b.z);
-    const float h = (float)(R.L * 2.3283064365386963e-10);
-    d2 = (ex * ex + ey * ey + ez * ez) * (h * h);
-    if (!fin) set_err(d.err, KAMD_DEV_NONFINITE);
-}
-
-// Per-replica maximum of the wavefront maxima of one block, one atomicMax per
-// replica present in the block (a block holds 4 consecutive wavefronts, which
-// may straddle two replicas).  All threads of the block must call it.
-__device__ inline void block_disp_max(const Dev &d, bool valid, int rep, float d2)
-{
-    __shared__ float wmax[WAVES_PER_BLOCK];
-    __shared__ int wrep[WAVES_PER_BLOCK];
-    d2 = wave_max(d2);
-    const int wv = threadIdx.x >> 6;
-    if (lane_id() == 0) {
-        wmax[wv] = d2;
-        wrep[wv] = valid ? rep : -1;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        // read first: the maximum only grows during the step, so most blocks
-        // find it already larger and skip the atomic
-        auto push = [&](int r, float m) {
-            const uint32_t bits = __float_as_uint(m);
-            const uint32_t cur = __hip_atomic_load(&d.maxdisp[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (bits > cur) atomicMax(&d.maxdisp[r], bits);
-        };
-        int r = -1;
-        float m = 0.0f;
-        for (int k = 0; k < WAVES_PER_BLOCK; ++k) {
-            if (wrep[k] != r) {
-                if (r >= 0) push(r, m);
-                r = wrep[k];
-                m = 0.0f;
-            }
-            m = fmaxf(m, wmax[k]);
-        }
-        if (r >= 0) push(r, m);
-    }
-}
-
 __global__ __launch_bounds__(BLOCK) void k_drift(Dev d, double dt, int nh)
 {
     SlotCtx c;
@@ -133,9 +52,9 @@ __global__ __launch_bounds__(BLOCK) void k_drift(Dev d, double dt, int nh)
             const RepDyn &D = d.dyn[c.rep];
             xi = D.xi; xia = D.xia; ck = D.c_kick;
         }
-        drift_one(d, c.s, c.rep, dt, xi, xia, ck, d2);
+        drift_one(d, c.s, c.rep, dt, xi, xia, ck, d.mirror, d2);
     }
-    block_disp_max(d, valid, valid ? c.rep : -1, d2);
+    block_disp_max(d.maxdisp, valid, valid ? c.rep : -1, d2);
 }
 
 // v = v_h + c a, with c the replica's kick factor; optional per-wave sum v^2.
@@ -175,13 +94,13 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(Dev d, double dt, int want
         const double vz = fma(h, d.az[s], d.vz[s]);
         k2 = vx * vx + vy * vy + vz * vz;
         d.vx[s] = vx; d.vy[s] = vy; d.vz[s] = vz;
-        drift_one(d, s, c.rep, dt, 0.0, 0.0, h, d2);
+        drift_one(d, s, c.rep, dt, 0.0, 0.0, h, d.mirror, d2);
     }
     if (want_ke && valid) {
         k2 = wave_sum(k2);
         if (lane_id() == 0) d.wred[4 * c.w + 0] = k2;
     }
-    block_disp_max(d, valid, valid ? c.rep : -1, d2);
+    block_disp_max(d.maxdisp, valid, valid ? c.rep : -1, d2);
 }
 
 // Per-replica sum of the 4 per-wave partials (fixed order).  what: 0 -> rsum.

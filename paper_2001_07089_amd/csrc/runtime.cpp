@@ -36,6 +36,8 @@ struct kamd_ctx {
     void *cells_alloc[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // count, start, end, seg
     void *nbr_alloc = nullptr;
     int64_t rdf_cells_cap = 0;
+    uint4 *mirror_alt = nullptr;      // second u32 mirror (fused force+drift steps)
+    uint32_t *md_base = nullptr;      // [2][n_rep] displacement maxima
     double *Q_dev = nullptr;
     double *obs_stage = nullptr;      // device [n_rep][4]
     double *state_tmp = nullptr;      // device caller-order staging for checkpoints
@@ -376,7 +378,9 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     TRY(dalloc(c, &d.order, np));
     TRY(dalloc(c, &d.nlen, np));
     TRY(dalloc(c, &d.rb_force, d.nrep));
-    TRY(dalloc(c, &d.maxdisp, d.nrep));
+    TRY(dalloc(c, &c->md_base, 2 * (size_t)d.nrep));
+    d.maxdisp = c->md_base;
+    TRY(dalloc(c, &c->mirror_alt, np));
     TRY(dalloc(c, &d.kmax, P.nwaves));
     TRY(dalloc(c, &d.wred, 4 * (size_t)P.nwaves));
     TRY(dalloc(c, &d.rsum, 4 * (size_t)d.nrep));
@@ -394,7 +398,8 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     HIPCHK(c, launch_zero_i32((int32_t *)d.smirror, 4 * np, c->stream));
     HIPCHK(c, launch_zero_i32(d.nlen, np, c->stream));
     HIPCHK(c, launch_zero_i32(d.rb_force, d.nrep, c->stream));
-    HIPCHK(c, launch_zero_i32((int32_t *)d.maxdisp, d.nrep, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)c->md_base, 2 * (int64_t)d.nrep, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)c->mirror_alt, 4 * np, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)d.kmax, 2 * (int64_t)P.nwaves, c->stream));
     HIPCHK(c, launch_zero_f64(d.wred, 4 * (int64_t)P.nwaves, c->stream));
     HIPCHK(c, launch_zero_f64((double *)d.dyn, 8 * (int64_t)d.nrep, c->stream));
@@ -483,9 +488,8 @@ static void lattice_positions(const kamd_replica &K, std::vector<double> &x, std
 }
 
 // ---------------------------------------------------------------- kernels
-static int rebuild_chain(kamd_ctx *c)
+static int rebuild_chain(kamd_ctx *c, const Dev &d)
 {
-    const Dev &d = c->d;
     HIPCHK(c, launch_rb_assign(d, c->stream));
     HIPCHK(c, launch_rb_scan(d, (int)c->segs.size(), c->stream));
     HIPCHK(c, launch_rb_scatter(d, c->stream));
@@ -504,14 +508,14 @@ static int force_rebuild_all(kamd_ctx *c)
 
 static int forces(kamd_ctx *c, bool energy)
 {
-    TRY(rebuild_chain(c));
+    TRY(rebuild_chain(c, c->d));
     HIPCHK(c, launch_force(c->d, c->model, c->cfg.precision, energy, false, c->stream));
     return KAMD_OK;
 }
 
 static int mb_reassign(kamd_ctx *c, bool device_tag, uint32_t tag)
 {
-    const Dev &d = c->d;
+    const Dev d = c->d;
     if (device_tag) HIPCHK(c, launch_mb_draw_dev(d, c->stream));
     else HIPCHK(c, launch_mb_draw(d, tag, c->stream));
     HIPCHK(c, launch_rep_reduce(d, 7, c->stream));
@@ -545,7 +549,7 @@ static int enqueue_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb
         for (int s = 1; s <= nsteps; ++s) {
             HIPCHK(c, launch_nh_begin(d, dt, c->Q_dev, c->stream));
             HIPCHK(c, launch_drift_nh(d, dt, c->stream));
-            TRY(rebuild_chain(c));
+            TRY(rebuild_chain(c, c->d));
             HIPCHK(c, launch_force(d, c->model, prec, false, true, c->stream));
             HIPCHK(c, launch_kick_nh(d, c->stream));
             HIPCHK(c, launch_rep_reduce(d, 1, c->stream));
@@ -554,22 +558,52 @@ static int enqueue_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb
         return KAMD_OK;
     }
     const bool stoch = ensemble == 1 && mode == KAMD_NVT_STOCHASTIC;
-    bool need_drift = true;
-    for (int s = 1; s <= nsteps; ++s) {
-        if (need_drift) HIPCHK(c, launch_drift(d, dt, c->stream));
-        TRY(rebuild_chain(c));
-        HIPCHK(c, launch_force(d, c->model, prec, false, true, c->stream));
+    // Mixed precisions fuse the force of a step with its closing half kick
+    // and the next drift whenever no thermostat acts in between.  Fused steps
+    // alternate the two position mirrors and the two displacement buffers;
+    // their number is made even so that every call starts and ends on the
+    // first buffers (which keeps graph replays consistent).
+    std::vector<char> fused(nsteps + 1, 0);
+    int nf = 0;
+    for (int s = 1; s < nsteps; ++s) {
         const int64_t gstep = c->step + s;
         const bool reassign = stoch && nb > 0 && (gstep % nb) == 0;
+        fused[s] = (prec != KAMD_PREC_FP64) && !reassign;
+        nf += fused[s];
+    }
+    if (nf % 2)
+        for (int s = 1; s < nsteps; ++s)
+            if (fused[s]) { fused[s] = 0; break; }
+    uint4 *mir[2] = {c->d.mirror, c->mirror_alt};
+    int cur = 0, par = 0;
+    Dev dd = c->d;
+    bool need_drift = true;
+    for (int s = 1; s <= nsteps; ++s) {
+        dd.mirror = mir[cur];
+        dd.maxdisp = c->md_base + par * c->d.nrep;
+        if (need_drift) HIPCHK(c, launch_drift(dd, dt, c->stream));
+        TRY(rebuild_chain(c, dd));
+        const int64_t gstep = c->step + s;
+        const bool reassign = stoch && nb > 0 && (gstep % nb) == 0;
+        if (fused[s]) {
+            HIPCHK(c, launch_force_kd(dd, c->model, prec, dt, mir[1 - cur], c->md_base + (1 - par) * c->d.nrep,
+                                      c->stream));
+            cur = 1 - cur;
+            par = 1 - par;
+            need_drift = false;
+            continue;
+        }
+        HIPCHK(c, launch_force(dd, c->model, prec, false, true, c->stream));
         if (s == nsteps || reassign) {
-            HIPCHK(c, launch_kick_nve(d, dt, false, c->stream));
+            HIPCHK(c, launch_kick_nve(dd, dt, false, c->stream));
             if (reassign) TRY(mb_reassign(c, device_tags, (uint32_t)gstep));
             need_drift = true;
         } else {
-            HIPCHK(c, launch_kick_drift(d, dt, false, c->stream));
+            HIPCHK(c, launch_kick_drift(dd, dt, false, c->stream));
             need_drift = false;
         }
     }
+    if (cur != 0 || par != 0) return fail(c, KAMD_EHIP, "internal: unbalanced mirror buffers");
     return KAMD_OK;
 }
 
@@ -711,7 +745,7 @@ extern "C" int md_build_cells(kamd_ctx *c)
 {
     if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
     TRY(force_rebuild_all(c));
-    TRY(rebuild_chain(c));
+    TRY(rebuild_chain(c, c->d));
     return KAMD_OK;
 }
 
@@ -1025,7 +1059,7 @@ extern "C" int md_set_state(kamd_ctx *c, const void *blob, size_t bytes)
     HIPCHK(c, hipMemcpyAsync(c->d.counters + 1, &host_step, 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     TRY(force_rebuild_all(c));
-    TRY(rebuild_chain(c));
+    TRY(rebuild_chain(c, c->d));
     return maybe_export(c);
 }
 
@@ -1094,51 +1128,73 @@ extern "C" int md_profile(kamd_ctx *c, int32_t nsteps, double *host_out)
 {
     if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");
     if (nsteps <= 0) return fail(c, KAMD_EINVAL, "nsteps must be > 0");
-    const Dev &d = c->d;
     const double dt = c->cfg.dt;
-    std::vector<hipEvent_t> ev(6 * (size_t)nsteps + 2);
+    const int prec = c->cfg.precision;
+    // the same step sequence as md_step_nve, with events around each part
+    std::vector<char> fused(nsteps + 1, 0);
+    int nf = 0;
+    for (int s = 1; s < nsteps; ++s) {
+        fused[s] = prec != KAMD_PREC_FP64;
+        nf += fused[s];
+    }
+    if (nf % 2)
+        for (int s = 1; s < nsteps; ++s)
+            if (fused[s]) { fused[s] = 0; break; }
+    std::vector<hipEvent_t> ev(5 * (size_t)nsteps + 2);
     for (auto &e : ev) HIPCHK(c, hipEventCreate(&e));
     int32_t cnt0[8], cnt1[8];
-    HIPCHK(c, hipMemcpyAsync(cnt0, d.counters, 32, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(cnt0, c->d.counters, 32, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    uint4 *mir[2] = {c->d.mirror, c->mirror_alt};
+    int cur = 0, par = 0;
+    Dev dd = c->d;
+    bool need_drift = true;
     size_t k = 0;
     HIPCHK(c, hipEventRecord(ev[k++], c->stream));
-    int rc = KAMD_OK;
-    for (int s = 1; s <= nsteps && !rc; ++s) {
-        // streaming pass before the forces (drift, or kick of the previous step + drift)
+    for (int s = 1; s <= nsteps; ++s) {
+        dd.mirror = mir[cur];
+        dd.maxdisp = c->md_base + par * c->d.nrep;
         HIPCHK(c, hipEventRecord(ev[k++], c->stream));
-        if (s == 1) HIPCHK(c, launch_drift(d, dt, c->stream));
-        else HIPCHK(c, launch_kick_drift(d, dt, false, c->stream));
+        if (need_drift) HIPCHK(c, launch_drift(dd, dt, c->stream));
         HIPCHK(c, hipEventRecord(ev[k++], c->stream));
-        rc = rebuild_chain(c);
+        TRY(rebuild_chain(c, dd));
         HIPCHK(c, hipEventRecord(ev[k++], c->stream));
-        HIPCHK(c, launch_force(d, c->model, c->cfg.precision, false, true, c->stream));
-        HIPCHK(c, hipEventRecord(ev[k++], c->stream));
-        if (s == nsteps) {
-            HIPCHK(c, hipEventRecord(ev[k++], c->stream));
-            HIPCHK(c, launch_kick_nve(d, dt, false, c->stream));
-            HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+        if (fused[s]) {
+            HIPCHK(c, launch_force_kd(dd, c->model, prec, dt, mir[1 - cur], c->md_base + (1 - par) * c->d.nrep,
+                                      c->stream));
+            cur = 1 - cur;
+            par = 1 - par;
+            need_drift = false;
+        } else {
+            HIPCHK(c, launch_force(dd, c->model, prec, false, true, c->stream));
         }
+        HIPCHK(c, hipEventRecord(ev[k++], c->stream));
+        if (!fused[s]) {
+            if (s == nsteps) {
+                HIPCHK(c, launch_kick_nve(dd, dt, false, c->stream));
+            } else {
+                HIPCHK(c, launch_kick_drift(dd, dt, false, c->stream));
+                need_drift = false;
+            }
+        }
+        HIPCHK(c, hipEventRecord(ev[k++], c->stream));
     }
     HIPCHK(c, hipEventRecord(ev[k++], c->stream));
     HIPCHK(c, hipEventSynchronize(ev[k - 1]));
     double tf = 0.0, ts = 0.0, tr = 0.0;
     float ms = 0.0f;
-    size_t q = 1;
-    for (int s = 1; s <= nsteps; ++s) {
+    for (int s = 0; s < nsteps; ++s) {
+        const size_t q = 1 + 5 * (size_t)s;
         HIPCHK(c, hipEventElapsedTime(&ms, ev[q], ev[q + 1])); ts += ms;
         HIPCHK(c, hipEventElapsedTime(&ms, ev[q + 1], ev[q + 2])); tr += ms;
         HIPCHK(c, hipEventElapsedTime(&ms, ev[q + 2], ev[q + 3])); tf += ms;
-        q += 4;
-        if (s == nsteps) {
-            HIPCHK(c, hipEventElapsedTime(&ms, ev[q], ev[q + 1])); ts += ms;
-            q += 2;
-        }
+        HIPCHK(c, hipEventElapsedTime(&ms, ev[q + 3], ev[q + 4])); ts += ms;
     }
     HIPCHK(c, hipEventElapsedTime(&ms, ev[0], ev[k - 1]));
     const double total = ms;
     for (auto &e : ev) (void)hipEventDestroy(e);
     c->step += nsteps;
+    const Dev &d = c->d;
     HIPCHK(c, hipMemcpyAsync(cnt1, d.counters, 32, hipMemcpyDeviceToHost, c->stream));
     // in-cutoff ordered pairs of the final configuration
     TRY(forces(c, true));
