@@ -22,6 +22,7 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;               // threads per block for slot kernels
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 constexpr int LIST_ROW_ALIGN = 4;        // neighbour rows are padded to this multiple
+constexpr int LIST_UNROLL = 8;           // candidates per step of the list builder's scan
 
 // Neighbour-list layout.  The list of wavefront w is a block of rows * 64
 // ints; entry k of lane l sits at (k / 4) * 256 + l * 4 + k % 4 inside it:

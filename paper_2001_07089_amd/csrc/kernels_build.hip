@@ -183,17 +183,22 @@ __global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
 //
 // The stencil is walked row by row: the cells of one stencil row differ only
 // in x and are consecutive in the cell-sorted slot order, so a row is one
-// contiguous slot range (two when it wraps around the box), scanned with
-// eight gathers in flight.  Rows, and the end cells of a row, that lie
-// farther than the list radius from the particle are skipped (in FP64, with a
-// margin, when the grid has at least 2*reach+1 cells per edge).
+// contiguous slot range (two when it wraps around the box), scanned eight
+// candidates at a time.  With cells as wide as the list radius (reach 1) all
+// particles of a cell walk the same 27 cells in the same order, so the lanes
+// of a wavefront that share a cell load the same addresses and one cache-line
+// access serves all of them; no per-particle pruning is done there, since it
+// would break that sharing for little gain.  With finer cells (reach 2) rows,
+// and the end cells of a row, that lie farther than the list radius from the
+// particle are skipped (in FP64, with a margin), which removes most of the
+// 125-cell stencil.  Grids with fewer than 2*reach+1 cells per edge scan
+// whole rows.
 //
 // Candidate test in u32 fixed-point units: the integer difference of two
 // coordinates is the minimum-image separation (the box maps onto the full
 // 2^32 range), converted to float; rl2_fx is enlarged by a few parts in 10^6
-// so that the list is a superset of the exact one.
-constexpr int LIST_UNROLL = 8;
-
+// so that the list is a superset of the exact one.  The sorted mirror has
+// LIST_UNROLL spare entries past its end, so the unrolled loads need no clamp.
 __device__ inline double gap(int o, int c, double cw, double u)
 {
     return o > 0 ? (c + o) * cw - u : (o < 0 ? u - (c + o + 1) * cw : 0.0);
@@ -232,7 +237,8 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     }
     const int nc = R.nc;
     const int noff = min(nc, 2 * reach + 1);
-    const bool prune = nc >= 2 * reach + 1;
+    const bool whole = nc < 2 * reach + 1;  // every cell of a row is in the stencil
+    const bool prune = !whole && reach > 1;
     const int cx = fix_cell(mi.x, nc), cy = fix_cell(mi.y, nc), cz = fix_cell(mi.z, nc);
     const double cw = 4294967296.0 / (double)nc;  // cell edge in fixed units
     const double ux = (double)mi.x, uy = (double)mi.y, uz = (double)mi.z;
@@ -249,9 +255,10 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         int cnt = 0;
         auto scan = [&](int st, int en) {
             for (int j = st; j < en; j += LIST_UNROLL) {
+                const uint4 *src = d.smirror + j;
                 uint4 mj[LIST_UNROLL];
 #pragma unroll
-                for (int u = 0; u < LIST_UNROLL; ++u) mj[u] = d.smirror[min(j + u, en - 1)];
+                for (int u = 0; u < LIST_UNROLL; ++u) mj[u] = src[u];
 #pragma unroll
                 for (int u = 0; u < LIST_UNROLL; ++u) {
                     const float dx = (float)(int)(mi.x - mj[u].x);
@@ -276,20 +283,22 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                     if (g2 > rp2) continue;
                     const int qy = (cy + oy + nc) % nc;
                     const int rowc = SJ.cell0 + (qz * nc + qy) * nc;  // cell (0, qy, qz)
-                    if (!prune) {  // every cell of the row is in the stencil
+                    if (whole) {
                         scan(d.cell_start[rowc], d.cell_end[rowc + nc - 1]);
                         continue;
                     }
                     int xl = -reach, xr = reach;
-                    while (xl < 0) {
-                        const double gx = gap(xl, cx, cw, ux);
-                        if (gx * gx + g2 <= rp2) break;
-                        ++xl;
-                    }
-                    while (xr > 0) {
-                        const double gx = gap(xr, cx, cw, ux);
-                        if (gx * gx + g2 <= rp2) break;
-                        --xr;
+                    if (prune) {
+                        while (xl < 0) {
+                            const double gx = gap(xl, cx, cw, ux);
+                            if (gx * gx + g2 <= rp2) break;
+                            ++xl;
+                        }
+                        while (xr > 0) {
+                            const double gx = gap(xr, cx, cw, ux);
+                            if (gx * gx + g2 <= rp2) break;
+                            --xr;
+                        }
                     }
                     const int a = cx + xl, b = cx + xr;  // unwrapped cell range [a, b]
                     if (a < 0) {

@@ -209,7 +209,7 @@ static size_t plan_bytes(const Plan &P, int n_rep)
     const size_t np = P.npad, nt = P.n_total;
     size_t b = 0;
     b += 2 * (9 * 8 + 3 * 4 + 4 + 16) * np;  // state + scratch
-    b += 16 * np;                              // mbuild
+    b += 16 * np + 16 * LIST_UNROLL;           // mbuild, tail of the sorted mirror
     b += 4 * np * 3;                           // cell_of, rank, order
     b += 4 * np;                               // nlen
     b += 4 * (size_t)P.ncells * 2;             // count/start
@@ -363,7 +363,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     TRY(dalloc(c, &d.sid, np));
     TRY(dalloc(c, &d.mirror, np));
     TRY(dalloc(c, &d.mbuild, np));
-    TRY(dalloc(c, &d.smirror, np));
+    TRY(dalloc(c, &d.smirror, np + LIST_UNROLL));  // the list scan reads up to 7 past a range
     SegInfo *sg;
     RepInfo *ri;
     int32_t *ws;
@@ -395,7 +395,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     HIPCHK(c, launch_zero_i32(d.img, 3 * np, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)d.mirror, 4 * np, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)d.mbuild, 4 * np, c->stream));
-    HIPCHK(c, launch_zero_i32((int32_t *)d.smirror, 4 * np, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.smirror, 4 * (np + LIST_UNROLL), c->stream));
     HIPCHK(c, launch_zero_i32(d.nlen, np, c->stream));
     HIPCHK(c, launch_zero_i32(d.rb_force, d.nrep, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)c->md_base, 2 * (int64_t)d.nrep, c->stream));
