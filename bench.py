@@ -26,7 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 19          # FP32 FLOPs per in-cutoff pair force (FMA = 2)
-FP32_VECTOR_PEAK = 157.3    # TFLOP/s, MI355X published dense vector peak
+# FP32 vector peak without packed-FP32 instructions (which this build does not
+# emit): 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz.  The published 157.3
+# TFLOP/s counts packed FP32 (two FMAs per lane per cycle).
+FP32_VECTOR_PEAK = 78.6     # TFLOP/s
+FP32_VECTOR_PEAK_PACKED = 157.3
+HBM_PEAK = 8000.0           # GB/s
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_hbm_traffic.md")
+TRAFFIC_SOURCES = ("paper_2001_07089_amd/csrc/kernels_force.hip", "paper_2001_07089_amd/csrc/common_dev.hpp",
+                   "paper_2001_07089_amd/csrc/kamd_internal.hpp")
 
 
 def log(*a):
@@ -42,6 +50,9 @@ def parse():
     p.add_argument("--precision", default="mixed_fixed", choices=["fp64", "mixed", "mixed_fixed"])
     p.add_argument("--equil", type=int, default=6000, help="stochastic-bath steps before timing")
     p.add_argument("--no-autotune", action="store_true")
+    p.add_argument("--skin", type=float, default=None, help="fixed list skin (skips the autotuner)")
+    p.add_argument("--cell-div", type=int, default=1, help="cell division with --skin")
+    p.add_argument("--no-analysis", action="store_true", help="skip the RDF / MSD timings")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU comparison run")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -86,6 +97,79 @@ def timed_graph(s, md, torch, steps):
     t1 = time.perf_counter()
     e1 = s.observables()[0, 4]
     return t1 - t0, e0, e1
+
+
+# Bytes per particle that the force launch must move besides its list: for
+# the fused mixed-precision step (forces, closing half kick, next drift) it
+# reads x,y,z,vx,vy,vz (48), the image counters (12), the u32 mirror (16) and
+# the mirror at the last list build (16), and writes x..vz (48), the image
+# counters (12) and the next mirror (16); the FP64 force-only kernel reads
+# x,y,z (24) and writes ax,ay,az (24).  Each list entry is a 4-byte index.
+STATE_BYTES = {"mixed": 168, "mixed_fixed": 168, "fp64": 48}
+
+
+def algorithmic_bytes(mean_list_len, n, precision):
+    return n * (4.0 * mean_list_len + STATE_BYTES[precision])
+
+
+def kernel_name(precision):
+    return {"fp64": "k_force_fp64<false>", "mixed": "k_force_mixed<false,false,true>",
+            "mixed_fixed": "k_force_mixed<true,false,true>"}[precision]
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(skin, cell_div, precision, n):
+    """HBM bytes per launch of the force kernel from the committed counter
+    summary, when it was taken on the current kernel source at the same list
+    parameters, precision and size; otherwise None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    kv = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            kv[k.strip()] = v.strip().strip("`")
+    try:
+        ok = (kv["source_digest"] == source_digest() and abs(float(kv["skin"]) - skin) < 1e-9
+              and int(kv["cell_div"]) == cell_div and kv["precision"] == precision and int(kv["n_atoms"]) == n)
+        return float(kv["hbm_bytes_per_launch"]) if ok else None
+    except (KeyError, ValueError):
+        return None
+
+
+def time_analysis(s, md, rep):
+    """On-device RDF (r_max 5.0, 200 bins) and MSD (one origin, one measurement)
+    of the large system, each timed on its own (wall clock around a synced call)."""
+    import torch
+    dr = 5.0 / 200
+    s.rdf(dr, 200)  # warm (allocates the histogram grid)
+    s.stream.synchronize()
+    t0 = time.perf_counter()
+    h = s.rdf(dr, 200)
+    s.stream.synchronize()
+    t_rdf = time.perf_counter() - t0
+    counts = s._host(h).astype(np.int64)[0].sum(axis=1)
+    s.msd_set_origin(1)
+    s.step_nve(100)
+    s.stream.synchronize()
+    t0 = time.perf_counter()
+    m = s.msd(1)
+    t_msd = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    return {"rdf_ms": t_rdf * 1e3, "rdf_r_max": 5.0, "rdf_bins": 200,
+            "rdf_pair_counts_AA_AB_BB": [int(c) for c in counts],
+            "msd_ms": t_msd * 1e3, "msd_after_100_steps_A_B": [float(m[0, 0]), float(m[0, 1])]}
 
 
 def cpu_baseline(wl, seconds):
@@ -178,8 +262,11 @@ def main():
     first = min(1000, a.equil)
     equilibrate(s, md, first)
     tune = None
-    if not a.no_autotune:
-        tune = md.md_autotune(s.ctx, 60)
+    if a.skin is not None:
+        md.md_set_list_params(s.ctx, a.skin, a.cell_div)
+        log(f"list parameters fixed: skin {a.skin}, cell_div {a.cell_div}")
+    elif not a.no_autotune:
+        tune = md.md_autotune(s.ctx, 100)
         log(f"autotune: {tune}")
     if a.equil > first:
         s.step_nvt(a.equil - first, md.NVT_STOCHASTIC, n_reassign=50)
@@ -196,14 +283,26 @@ def main():
     w = s.status()
     log(f"profile: {prof}")
     log(f"stats: {st}  err=0x{w:x}")
+    skin = st["skin"]
     pairs = prof["pairs"]
     flops = pairs * FLOP_PER_PAIR
     achieved = flops / (prof["force_ms"] * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK, "unit": "TFLOP/s",
-            "frac": achieved / FP32_VECTOR_PEAK, "traffic": None,
-            "kernel": f"force_{a.precision}", "kernel_ms": prof["force_ms"],
-            "ordered_pairs_per_launch": pairs}
-    skin = st["skin"]
+    candidates = st["mean_list_len"] * n
+    traffic = stored_traffic(skin, int(st["cell_div"]), a.precision, n)
+    alg = algorithmic_bytes(st["mean_list_len"], n, a.precision)
+    gbs = alg / (prof["force_ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK, "unit": "GB/s", "frac": gbs / HBM_PEAK,
+            "traffic": traffic, "kernel": kernel_name(a.precision), "kernel_ms": prof["force_ms"],
+            "algorithmic_bytes_per_launch": alg,
+            "traffic_over_algorithmic": (traffic / alg) if traffic else None,
+            "alu_view": {"useful_tflops": achieved, "issued_tflops":
+                         candidates * FLOP_PER_PAIR / (prof["force_ms"] * 1e-3) / 1e12,
+                         "peak_tflops": FP32_VECTOR_PEAK, "frac": achieved / FP32_VECTOR_PEAK,
+                         "frac_of_packed_peak": achieved / FP32_VECTOR_PEAK_PACKED,
+                         "ordered_pairs_per_launch": pairs, "list_candidates_per_launch": candidates}}
+    analysis = None if a.no_analysis else time_analysis(s, md, rep)
+    if analysis:
+        log(f"analysis: {analysis}")
     s.close()
     del s
     torch.cuda.empty_cache()
@@ -260,6 +359,7 @@ def main():
         "batched": batch,
         "cpu_baseline": cpu,
         "autotune": tune,
+        "analysis": analysis,
     }
     print(json.dumps(out), flush=True)
 

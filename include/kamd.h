@@ -227,8 +227,10 @@ int md_graph_launch(kamd_ctx *ctx);
 
 /* Neighbour-list tuning: time probe_steps NVE steps for each candidate skin
  * (0.2 .. min(0.5, L/2 - r_c,max)) and each cell division (1, 2) on a copy
- * of the current state, keep the fastest, restore the state.  Results in
- * host_out (host, FP64 [3]): {skin, cell_div, ms_per_step}.  Syncs. */
+ * of the current state, restore the state, and keep the smallest skin (then
+ * the coarser grid) whose time is within 1% of the fastest probe.  Results
+ * in host_out (host, FP64 [3]): {skin, cell_div, ms_per_step of the kept
+ * candidate}.  Syncs. */
 int md_autotune(kamd_ctx *ctx, int32_t probe_steps, double *host_out);
 
 /* Change skin and cell division (forces a rebuild at the next step). */

@@ -1079,8 +1079,12 @@ extern "C" int md_autotune(kamd_ctx *c, int32_t probe_steps, double *host_out)
     std::vector<double> skins;
     for (double s : {0.2, 0.25, 0.3, 0.35, 0.4, 0.5})
         if (c->rc_max + s < 0.5 * Lmin || s <= 0.2) skins.push_back(s);
-    double best_t = 1e300, best_s = skin0;
-    int best_d = div0;
+    struct Probe {
+        double skin;
+        int div;
+        double ms;
+    };
+    std::vector<Probe> probes;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -1102,13 +1106,23 @@ extern "C" int md_autotune(kamd_ctx *c, int32_t probe_steps, double *host_out)
             (void)hipEventElapsedTime(&ms, e0, e1);
             uint32_t word = 0;
             (void)hipMemcpy(&word, c->d.err, 4, hipMemcpyDeviceToHost);
-            if (word == 0 && ms / probe_steps < best_t) {
-                best_t = ms / probe_steps;
-                best_s = s;
-                best_d = dv;
-            }
+            if (word == 0) probes.push_back({s, dv, (double)ms / probe_steps});
         }
         if (rc) break;
+    }
+    // Within 1% of the fastest probe the timings are not told apart reliably
+    // (a probe sees only a few rebuilds); take the smallest skin, then the
+    // coarser grid, among those, which also needs the least list memory.
+    double fastest = 1e300, best_t = 1e300, best_s = skin0;
+    int best_d = div0;
+    for (const Probe &p : probes) fastest = std::min(fastest, p.ms);
+    for (const Probe &p : probes) {  // ordered by skin, then by grid
+        if (p.ms <= 1.01 * fastest) {
+            best_s = p.skin;
+            best_d = p.div;
+            best_t = p.ms;
+            break;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

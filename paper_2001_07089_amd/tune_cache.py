@@ -1,0 +1,89 @@
+"""Persistent cache of the neighbour-list parameters chosen by ``md_autotune``.
+
+Probing every candidate skin and cell grid costs about a thousand steps, so
+the choice is stored in a JSON file and reused by later runs of the same
+workload class on the same device.  The key is built from the device name,
+the precision mode and coarse buckets of what the choice depends on: total
+particle count (power of two), replica count (power of two), number density
+(0.05) and mean temperature (0.25).  A hit applies the stored skin and grid
+with ``md_set_list_params``; a miss runs ``md_autotune`` and records its
+result.  Writes go to a temporary file that replaces the cache atomically.
+"""
+import json
+import math
+import os
+
+from . import md
+
+PRECISION_NAMES = {md.PREC_FP64: "fp64", md.PREC_MIXED: "mixed", md.PREC_MIXED_FIXED: "mixed_fixed"}
+
+
+def default_path() -> str:
+    env = os.environ.get("KAMD_TUNE_CACHE")
+    if env:
+        return env
+    return os.path.join(os.path.expanduser("~"), ".cache", "kamd", "autotune.json")
+
+
+def workload_key(device: str, precision: int, reps) -> str:
+    """Cache key of a replica set (ctypes Replica array or objects with n, box,
+    temperature attributes)."""
+    reps = list(reps)
+    n_total = sum(int(r.n) for r in reps)
+    rho = sum(r.n / r.box ** 3 for r in reps) / len(reps)
+    temp = sum(r.temperature for r in reps) / len(reps)
+    return "|".join([
+        device,
+        PRECISION_NAMES.get(int(precision), str(precision)),
+        f"n2^{int(math.floor(math.log2(max(n_total, 1))))}",
+        f"r2^{int(math.floor(math.log2(len(reps))))}",
+        f"rho{round(rho / 0.05) * 0.05:.2f}",
+        f"T{round(temp / 0.25) * 0.25:.2f}",
+    ])
+
+
+def load(path: str) -> dict:
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return {}
+    return data if isinstance(data, dict) else {}
+
+
+def store(path: str, key: str, entry: dict) -> None:
+    data = load(path)
+    data[key] = entry
+    d = os.path.dirname(path)
+    if d:
+        os.makedirs(d, exist_ok=True)
+    tmp = f"{path}.{os.getpid()}.tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def device_name(torch_module=None) -> str:
+    import torch
+    t = torch_module or torch
+    p = t.cuda.get_device_properties(t.cuda.current_device())
+    arch = getattr(p, "gcnArchName", "")
+    return f"{p.name}:{arch}" if arch else p.name
+
+
+def tune(system, probe_steps: int = 100, path: str = None, device: str = None, refresh: bool = False) -> dict:
+    """List parameters for ``system`` (an ``md.System``): from the cache when the
+    key is present (and ``refresh`` is false), else from ``md_autotune``.
+    Returns {"skin", "cell_div", "ms_per_step", "cached", "key"}."""
+    path = path or default_path()
+    device = device or device_name(getattr(system, "torch", None))
+    key = workload_key(device, system.cfg.precision, system.reps)
+    hit = None if refresh else load(path).get(key)
+    if hit and "skin" in hit and "cell_div" in hit:
+        md.md_set_list_params(system.ctx, float(hit["skin"]), int(hit["cell_div"]))
+        return {"skin": float(hit["skin"]), "cell_div": int(hit["cell_div"]),
+                "ms_per_step": hit.get("ms_per_step"), "cached": True, "key": key}
+    res = md.md_autotune(system.ctx, probe_steps)
+    store(path, key, {"skin": res["skin"], "cell_div": res["cell_div"], "ms_per_step": res["ms_per_step"],
+                      "probe_steps": int(probe_steps)})
+    return dict(res, cached=False, key=key)

@@ -1,0 +1,73 @@
+"""Host logic of the autotuner cache: keys, hit/miss behaviour, atomic JSON
+storage.  The two library calls are replaced by recording fakes, so this runs
+without a GPU."""
+import json
+import types
+
+import pytest
+
+from paper_2001_07089_amd import md, tune_cache
+from paper_2001_07089_amd import workload as W
+
+
+def _system(reps, precision="mixed_fixed"):
+    cfg = md.make_config(precision)
+    return types.SimpleNamespace(ctx="CTX", cfg=cfg, reps=md.make_replicas(reps))
+
+
+@pytest.fixture
+def fakes(monkeypatch):
+    calls = {"tune": 0, "set": []}
+
+    def fake_tune(ctx, probe_steps=100):
+        calls["tune"] += 1
+        return {"skin": 0.4, "cell_div": 1, "ms_per_step": 0.43}
+
+    def fake_set(ctx, skin, cell_div):
+        calls["set"].append((skin, cell_div))
+
+    monkeypatch.setattr(md, "md_autotune", fake_tune)
+    monkeypatch.setattr(md, "md_set_list_params", fake_set)
+    return calls
+
+
+def test_miss_then_hit(tmp_path, fakes):
+    r = W.ka_large().replicas[0]
+    s = _system([(r.n, r.n_a, r.box, r.temperature, r.seed)])
+    path = str(tmp_path / "c" / "tune.json")
+    a = tune_cache.tune(s, 50, path=path, device="MI355X:gfx950")
+    assert not a["cached"] and fakes["tune"] == 1 and fakes["set"] == []
+    b = tune_cache.tune(s, 50, path=path, device="MI355X:gfx950")
+    assert b["cached"] and fakes["tune"] == 1 and fakes["set"] == [(0.4, 1)]
+    assert (b["skin"], b["cell_div"]) == (a["skin"], a["cell_div"])
+    data = json.load(open(path))
+    assert list(data) == [a["key"]] and data[a["key"]]["probe_steps"] == 50
+    c = tune_cache.tune(s, 50, path=path, device="MI355X:gfx950", refresh=True)
+    assert not c["cached"] and fakes["tune"] == 2
+
+
+def test_key_separates_device_precision_and_workload():
+    r = W.ka_large().replicas[0]
+    one = md.make_replicas([(r.n, r.n_a, r.box, r.temperature, r.seed)])
+    k = tune_cache.workload_key("dev", md.PREC_MIXED_FIXED, one)
+    assert k != tune_cache.workload_key("other", md.PREC_MIXED_FIXED, one)
+    assert k != tune_cache.workload_key("dev", md.PREC_FP64, one)
+    small = W.ka_small().replicas[0]
+    assert k != tune_cache.workload_key("dev", md.PREC_MIXED_FIXED,
+                                        md.make_replicas([(small.n, small.n_a, small.box, 0.45, 1)]))
+    batch = W.ka_batch_small()
+    kb = tune_cache.workload_key("dev", md.PREC_MIXED, md.make_replicas(batch.replicas))
+    assert "r2^8" in kb and "rho1.20" in kb
+    # a different seed (same class) maps to the same key
+    assert k == tune_cache.workload_key("dev", md.PREC_MIXED_FIXED,
+                                        md.make_replicas([(r.n, r.n_a, r.box, r.temperature, r.seed + 7)]))
+
+
+def test_corrupt_cache_is_a_miss(tmp_path, fakes):
+    path = tmp_path / "tune.json"
+    path.write_text("{not json")
+    r = W.ka_small().replicas[0]
+    s = _system([(r.n, r.n_a, r.box, r.temperature, r.seed)], "fp64")
+    out = tune_cache.tune(s, 10, path=str(path), device="d")
+    assert not out["cached"] and fakes["tune"] == 1
+    assert out["key"] in json.load(open(path))
