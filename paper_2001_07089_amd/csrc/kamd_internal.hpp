@@ -108,6 +108,7 @@ struct Dev {
     // cells and lists
     int32_t *cell_of, *rank, *cell_count, *cell_start, *cell_end, *order;
     int32_t *rb_force;    // per replica: rebuild at the next check regardless
+    int32_t *rb_any;      // [1]: some replica rebuilds this step (set by the chain's gate kernel)
     uint32_t *maxdisp;    // per replica: max |r - r_build|^2 (float bits) since the last check
     int32_t *nbr;         // per wave: rows x 64 entries, see list_index
     int2 *kmax;           // per wave: rows of the A part, rows of the B part
@@ -138,6 +139,7 @@ struct Dev {
 
 // ---------------------------------------------------------------- launchers
 // Each returns hipGetLastError() after its launch(es).
+hipError_t launch_rb_gate(const Dev &d, hipStream_t s);
 hipError_t launch_rb_assign(const Dev &d, hipStream_t s);
 hipError_t launch_rb_scan(const Dev &d, int nseg, hipStream_t s);
 hipError_t launch_rb_scatter(const Dev &d, hipStream_t s);

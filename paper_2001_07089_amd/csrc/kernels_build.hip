@@ -27,10 +27,21 @@
 
 namespace kamd {
 
-__global__ __launch_bounds__(BLOCK) void k_rb_assign(Dev d)
+// The gate: one block ORs the rebuild flags of all replicas into rb_any, so
+// that on the (most frequent) steps without a rebuild every later kernel of
+// the chain exits after one load.
+__global__ __launch_bounds__(BLOCK) void k_rb_gate(Dev d)
 {
-    const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    if (w >= d.nwaves) return;
+    int any = 0;
+    for (int r = threadIdx.x; r < d.nrep; r += BLOCK) any |= rebuild_flag(d, r) ? 1 : 0;
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) d.rb_any[0] = any;
+}
+
+// The per-particle kernels of the chain walk their work units
+// with a grid stride over a capped grid (their work per unit is small).
+__device__ inline void assign_wave(const Dev &d, int w)
+{
     const SegInfo &S = d.seg[d.wave_seg[w]];
     if (!rebuild_flag(d, S.rep)) return;
     const int lane = lane_id();
@@ -57,7 +68,13 @@ __global__ __launch_bounds__(BLOCK) void k_rb_assign(Dev d)
     if (head && real) base = atomicAdd(&d.cell_count[c], next - lane);
     base = __shfl(base, first, 64);
     if (real) d.rank[s] = base + (lane - first);
-    (void)next;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rb_assign(Dev d)
+{
+    if (d.rb_any[0] == 0) return;
+    const int stride = gridDim.x * WAVES_PER_BLOCK;
+    for (int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); w < d.nwaves; w += stride) assign_wave(d, w);
 }
 
 // Exclusive scan of one segment's cell counters into absolute slot ranges
@@ -68,6 +85,7 @@ __global__ __launch_bounds__(1024) void k_rb_scan(Dev d)
 {
     __shared__ int wtot[16];
     __shared__ int carry_s;
+    if (d.rb_any[0] == 0) return;
     const SegInfo &S = d.seg[blockIdx.x];
     if (!rebuild_flag(d, S.rep)) return;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
@@ -117,13 +135,14 @@ __global__ __launch_bounds__(1024) void k_rb_scan(Dev d)
 
 __global__ __launch_bounds__(BLOCK) void k_rb_scatter(Dev d)
 {
-    const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    if (w >= d.nwaves) return;
-    const SegInfo &S = d.seg[d.wave_seg[w]];
-    if (!rebuild_flag(d, S.rep)) return;
-    const int s = w * WAVE + lane_id();
-    if (s - S.slot0 >= S.n) return;
-    d.order[d.cell_start[d.cell_of[s]] + d.rank[s]] = s;
+    if (d.rb_any[0] == 0) return;
+    const int stride = gridDim.x * WAVES_PER_BLOCK;
+    for (int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); w < d.nwaves; w += stride) {
+        const SegInfo &S = d.seg[d.wave_seg[w]];
+        if (!rebuild_flag(d, S.rep)) continue;
+        const int s = w * WAVE + lane_id();
+        if (s - S.slot0 < S.n) d.order[d.cell_start[d.cell_of[s]] + d.rank[s]] = s;
+    }
 }
 
 __device__ inline void gather_one(const Dev &d, int v, int t)
@@ -149,10 +168,8 @@ __device__ inline void gather_one(const Dev &d, int v, int t)
 // previous slot, which makes the counting sort stable.  Cells of up to 64
 // members rank in registers; larger ones (only tiny boxes with 1-2 cells per
 // edge) fall back to a loop over memory.
-__global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
+__device__ inline void sortgather_cell(const Dev &d, int c)
 {
-    const int c = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    if (c >= d.ncells) return;
     const SegInfo &S = d.seg[d.cell_seg[c]];
     if (!rebuild_flag(d, S.rep)) return;
     const int st = d.cell_start[c];
@@ -172,6 +189,13 @@ __global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
         }
     }
     if (lane == 0) d.cell_count[c] = 0;  // ready for the next rebuild
+}
+
+__global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
+{
+    if (d.rb_any[0] == 0) return;
+    const int c = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    if (c < d.ncells) sortgather_cell(d, c);
 }
 
 // Neighbour lists.  One thread per particle.  Entries [0, kA) of a list hold
@@ -204,8 +228,17 @@ __device__ inline double gap(int o, int c, double cw, double u)
     return o > 0 ? (c + o) * cw - u : (o < 0 ? u - (c + o + 1) * cw : 0.0);
 }
 
+// Accepted entries are staged in LDS, LIST_STAGE per lane, and written out
+// four at a time (one 16-byte store per lane) when some lane's stage fills.
+// Staging keeps stores out of the scan loop: on this architecture a wait for
+// loaded data also waits for every store issued before those loads, so a
+// store per candidate batch would expose the store latency on every batch.
+constexpr int LIST_STAGE = 32;
+
 __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
 {
+    __shared__ int32_t stage[WAVES_PER_BLOCK][LIST_STAGE][WAVE];
+    if (d.rb_any[0] == 0) return;
     const int w = wave_id_remapped();  // each XCD walks a contiguous slot range
     if (w >= d.nwaves) return;
     const SegInfo &S = d.seg[d.wave_seg[w]];
@@ -243,6 +276,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     const double cw = 4294967296.0 / (double)nc;  // cell edge in fixed units
     const double ux = (double)mi.x, uy = (double)mi.y, uz = (double)mi.z;
     int32_t *col = d.nbr + list_index(w, d.rows, 0, lane);
+    int32_t(*buf)[WAVE] = stage[threadIdx.x / WAVE];
     const int rows = d.rows;
     int row = 0;
     int total = 0;
@@ -252,7 +286,22 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         const float rl2 = R.rl2_fx[S.type + tj];
         const double rp = sqrt((double)rl2) + 4096.0;  // pruning radius with margin
         const double rp2 = rp * rp;
-        int cnt = 0;
+        int cnt = 0;   // entries accepted
+        int done = 0;  // entries written to the list (a multiple of 4)
+        auto flush = [&]() {  // write every complete group of four staged entries
+            while (done + 4 <= cnt) {
+                const int k = row + done;
+                const int4 q = make_int4(buf[done & (LIST_STAGE - 1)][lane], buf[(done + 1) & (LIST_STAGE - 1)][lane],
+                                         buf[(done + 2) & (LIST_STAGE - 1)][lane],
+                                         buf[(done + 3) & (LIST_STAGE - 1)][lane]);
+                if (k < rows) *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = q;
+                done += 4;
+            }
+        };
+        // Each candidate is written to the next free stage slot whether or
+        // not it is accepted; only an accepted one advances the count.  At
+        // the start of a batch at most LIST_STAGE - LIST_UNROLL entries are
+        // pending, so the slot written is never one still to be flushed.
         auto scan = [&](int st, int en) {
             for (int j = st; j < en; j += LIST_UNROLL) {
                 const uint4 *src = d.smirror + j;
@@ -265,12 +314,11 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                     const float dy = (float)(int)(mi.y - mj[u].y);
                     const float dz = (float)(int)(mi.z - mj[u].z);
                     const float r2 = dx * dx + dy * dy + dz * dz;
-                    if (j + u < en && r2 < rl2 && r2 > 0.0f) {
-                        const int k = row + cnt;
-                        if (k < rows) col[(k >> 2) * 256 + (k & 3)] = j + u;
-                        ++cnt;
-                    }
+                    const int acc = (int)(j + u < en) & (int)(r2 < rl2) & (int)(r2 > 0.0f);
+                    buf[cnt & (LIST_STAGE - 1)][lane] = j + u;
+                    cnt += acc;
                 }
+                if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
             }
         };
         if (real && SJ.n > 0) {
@@ -313,10 +361,20 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                 }
             }
         }
+        flush();
         total += cnt;
         int kmax = wave_max_i(cnt);
         kmax = (kmax + LIST_ROW_ALIGN - 1) / LIST_ROW_ALIGN * LIST_ROW_ALIGN;
-        for (int k = row + cnt; k < row + kmax && k < rows; ++k) col[(k >> 2) * 256 + (k & 3)] = s;
+        if (done < cnt) {  // the last partial group, padded with the particle's own slot
+            const int k = row + done;
+            int e[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) e[t] = done + t < cnt ? buf[(done + t) & (LIST_STAGE - 1)][lane] : s;
+            if (k < rows) *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = make_int4(e[0], e[1], e[2], e[3]);
+            done += 4;
+        }
+        for (int k = row + done; k < row + kmax && k < rows; k += 4)
+            *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = make_int4(s, s, s, s);
         if (row + kmax > rows && lane == 0) set_err(d.err, KAMD_DEV_LIST_OVERFLOW);
         kpart[tj] = kmax;
         row += kmax;
@@ -330,10 +388,17 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
 }
 
 static inline int nblk_slots(const Dev &d) { return (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
+constexpr int CHAIN_MAX_BLOCKS = 1024;  // grid cap of the grid-stride chain kernels
+static inline int nblk_capped(int waves) { return std::min((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, CHAIN_MAX_BLOCKS); }
 
+hipError_t launch_rb_gate(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rb_gate, dim3(1), dim3(BLOCK), 0, s, d);
+    return hipGetLastError();
+}
 hipError_t launch_rb_assign(const Dev &d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rb_assign, dim3(nblk_slots(d)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_rb_assign, dim3(nblk_capped(d.nwaves)), dim3(BLOCK), 0, s, d);
     return hipGetLastError();
 }
 hipError_t launch_rb_scan(const Dev &d, int nseg, hipStream_t s)
@@ -343,7 +408,7 @@ hipError_t launch_rb_scan(const Dev &d, int nseg, hipStream_t s)
 }
 hipError_t launch_rb_scatter(const Dev &d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rb_scatter, dim3(nblk_slots(d)), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_rb_scatter, dim3(nblk_capped(d.nwaves)), dim3(BLOCK), 0, s, d);
     return hipGetLastError();
 }
 hipError_t launch_rb_sortgather(const Dev &d, hipStream_t s)

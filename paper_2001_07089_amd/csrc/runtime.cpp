@@ -378,6 +378,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     TRY(dalloc(c, &d.order, np));
     TRY(dalloc(c, &d.nlen, np));
     TRY(dalloc(c, &d.rb_force, d.nrep));
+    TRY(dalloc(c, &d.rb_any, 1));
     TRY(dalloc(c, &c->md_base, 2 * (size_t)d.nrep));
     d.maxdisp = c->md_base;
     TRY(dalloc(c, &c->mirror_alt, np));
@@ -398,6 +399,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     HIPCHK(c, launch_zero_i32((int32_t *)d.smirror, 4 * (np + LIST_UNROLL), c->stream));
     HIPCHK(c, launch_zero_i32(d.nlen, np, c->stream));
     HIPCHK(c, launch_zero_i32(d.rb_force, d.nrep, c->stream));
+    HIPCHK(c, launch_zero_i32(d.rb_any, 1, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)c->md_base, 2 * (int64_t)d.nrep, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)c->mirror_alt, 4 * np, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)d.kmax, 2 * (int64_t)P.nwaves, c->stream));
@@ -490,6 +492,7 @@ static void lattice_positions(const kamd_replica &K, std::vector<double> &x, std
 // ---------------------------------------------------------------- kernels
 static int rebuild_chain(kamd_ctx *c, const Dev &d)
 {
+    HIPCHK(c, launch_rb_gate(d, c->stream));
     HIPCHK(c, launch_rb_assign(d, c->stream));
     HIPCHK(c, launch_rb_scan(d, (int)c->segs.size(), c->stream));
     HIPCHK(c, launch_rb_scatter(d, c->stream));
