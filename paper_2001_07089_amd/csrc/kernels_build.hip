@@ -23,6 +23,8 @@
 //                 particles' state into the scratch arrays, clear the counter
 //   rb_list       per particle: copy its state back, record the build
 //                 position, write its neighbour list
+#include <climits>
+
 #include "common_dev.hpp"
 
 namespace kamd {
@@ -233,11 +235,22 @@ __device__ inline double gap(int o, int c, double cw, double u)
 // Staging keeps stores out of the scan loop: on this architecture a wait for
 // loaded data also waits for every store issued before those loads, so a
 // store per candidate batch would expose the store latency on every batch.
-constexpr int LIST_STAGE = 32;
+//
+// Candidate positions are staged too.  With one cell per list radius every
+// particle scans, per stencil row, at most three pieces: the wrapped high
+// end of the row, the main run of cells, the wrapped low end.  For each
+// piece the wavefront loads the union of its lanes' slot ranges into LDS
+// once, with coalesced loads, and the lanes then scan their own ranges out
+// of LDS; lanes of one cell read the same LDS words (a broadcast).  A union
+// longer than LIST_WIN (lanes in different rows of the grid) is scanned
+// straight from global memory instead.
+constexpr int LIST_STAGE = 16;
+constexpr int LIST_WIN = 384;
 
 __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
 {
     __shared__ int32_t stage[WAVES_PER_BLOCK][LIST_STAGE][WAVE];
+    __shared__ uint32_t win_s[WAVES_PER_BLOCK][3][LIST_WIN + LIST_UNROLL];
     if (d.rb_any[0] == 0) return;
     const int w = wave_id_remapped();  // each XCD walks a contiguous slot range
     if (w >= d.nwaves) return;
@@ -277,6 +290,9 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     const double ux = (double)mi.x, uy = (double)mi.y, uz = (double)mi.z;
     int32_t *col = d.nbr + list_index(w, d.rows, 0, lane);
     int32_t(*buf)[WAVE] = stage[threadIdx.x / WAVE];
+    uint32_t *wx = win_s[threadIdx.x / WAVE][0];
+    uint32_t *wy = win_s[threadIdx.x / WAVE][1];
+    uint32_t *wz = win_s[threadIdx.x / WAVE][2];
     const int rows = d.rows;
     int row = 0;
     int total = 0;
@@ -302,41 +318,64 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         // not it is accepted; only an accepted one advances the count.  At
         // the start of a batch at most LIST_STAGE - LIST_UNROLL entries are
         // pending, so the slot written is never one still to be flushed.
-        auto scan = [&](int st, int en) {
+        auto test = [&](int j, int en, uint32_t jx, uint32_t jy, uint32_t jz) {
+            const float dx = (float)(int)(mi.x - jx);
+            const float dy = (float)(int)(mi.y - jy);
+            const float dz = (float)(int)(mi.z - jz);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const int acc = (int)(j < en) & (int)(r2 < rl2) & (int)(r2 > 0.0f);
+            buf[cnt & (LIST_STAGE - 1)][lane] = j;
+            cnt += acc;
+        };
+        auto scan = [&](int st, int en) {  // straight from global memory
             for (int j = st; j < en; j += LIST_UNROLL) {
                 const uint4 *src = d.smirror + j;
                 uint4 mj[LIST_UNROLL];
 #pragma unroll
                 for (int u = 0; u < LIST_UNROLL; ++u) mj[u] = src[u];
 #pragma unroll
-                for (int u = 0; u < LIST_UNROLL; ++u) {
-                    const float dx = (float)(int)(mi.x - mj[u].x);
-                    const float dy = (float)(int)(mi.y - mj[u].y);
-                    const float dz = (float)(int)(mi.z - mj[u].z);
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    const int acc = (int)(j + u < en) & (int)(r2 < rl2) & (int)(r2 > 0.0f);
-                    buf[cnt & (LIST_STAGE - 1)][lane] = j + u;
-                    cnt += acc;
-                }
+                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, en, mj[u].x, mj[u].y, mj[u].z);
                 if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
             }
         };
-        if (real && SJ.n > 0) {
-            for (int oz = -reach; oz < -reach + noff; ++oz) {
-                const double gz = prune ? fmax(gap(oz, cz, cw, uz), 0.0) : 0.0;
-                const int qz = (cz + oz + nc) % nc;
-                for (int oy = -reach; oy < -reach + noff; ++oy) {
-                    const double gy = prune ? fmax(gap(oy, cy, cw, uy), 0.0) : 0.0;
-                    const double g2 = gy * gy + gz * gz;
-                    if (g2 > rp2) continue;
-                    const int qy = (cy + oy + nc) % nc;
-                    const int rowc = SJ.cell0 + (qz * nc + qy) * nc;  // cell (0, qy, qz)
-                    if (whole) {
-                        scan(d.cell_start[rowc], d.cell_end[rowc + nc - 1]);
-                        continue;
-                    }
-                    int xl = -reach, xr = reach;
-                    if (prune) {
+        auto scan_staged = [&](int st, int en) {  // all lanes of the wavefront take part
+            const bool has = st < en;
+            const int lo = -wave_max_i(has ? -st : INT_MIN + 1);
+            if (lo == INT_MAX) return;
+            const int hi = wave_max_i(has ? en : -1);
+            if (hi - lo > LIST_WIN) {
+                if (has) scan(st, en);
+                return;
+            }
+            for (int e = lane; e < hi - lo; e += WAVE) {
+                const uint4 m = d.smirror[lo + e];
+                wx[e] = m.x;
+                wy[e] = m.y;
+                wz[e] = m.z;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            for (int j = st; j < en; j += LIST_UNROLL) {
+                const int o = j - lo;
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, en, wx[o + u], wy[o + u], wz[o + u]);
+                if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        };
+        if (SJ.n > 0 && prune) {  // finer cells: per-particle pruning, direct scans
+            if (real) {
+                for (int oz = -reach; oz < -reach + noff; ++oz) {
+                    const double gz = fmax(gap(oz, cz, cw, uz), 0.0);
+                    const int qz = (cz + oz + nc) % nc;
+                    for (int oy = -reach; oy < -reach + noff; ++oy) {
+                        const double gy = fmax(gap(oy, cy, cw, uy), 0.0);
+                        const double g2 = gy * gy + gz * gz;
+                        if (g2 > rp2) continue;
+                        const int qy = (cy + oy + nc) % nc;
+                        const int rowc = SJ.cell0 + (qz * nc + qy) * nc;  // cell (0, qy, qz)
+                        int xl = -reach, xr = reach;
                         while (xl < 0) {
                             const double gx = gap(xl, cx, cw, ux);
                             if (gx * gx + g2 <= rp2) break;
@@ -347,17 +386,48 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                             if (gx * gx + g2 <= rp2) break;
                             --xr;
                         }
+                        const int a = cx + xl, b = cx + xr;  // unwrapped cell range [a, b]
+                        if (a < 0) {
+                            scan(d.cell_start[rowc + a + nc], d.cell_end[rowc + nc - 1]);
+                            scan(d.cell_start[rowc], d.cell_end[rowc + b]);
+                        } else if (b >= nc) {
+                            scan(d.cell_start[rowc + a], d.cell_end[rowc + nc - 1]);
+                            scan(d.cell_start[rowc], d.cell_end[rowc + b - nc]);
+                        } else {
+                            scan(d.cell_start[rowc + a], d.cell_end[rowc + b]);
+                        }
                     }
-                    const int a = cx + xl, b = cx + xr;  // unwrapped cell range [a, b]
-                    if (a < 0) {
-                        scan(d.cell_start[rowc + a + nc], d.cell_end[rowc + nc - 1]);
-                        scan(d.cell_start[rowc], d.cell_end[rowc + b]);
-                    } else if (b >= nc) {
-                        scan(d.cell_start[rowc + a], d.cell_end[rowc + nc - 1]);
-                        scan(d.cell_start[rowc], d.cell_end[rowc + b - nc]);
-                    } else {
-                        scan(d.cell_start[rowc + a], d.cell_end[rowc + b]);
+                }
+            }
+        } else if (SJ.n > 0) {  // every lane walks the same rows: staged scans
+            for (int oz = -reach; oz < -reach + noff; ++oz) {
+                const int qz = (cz + oz + nc) % nc;
+                for (int oy = -reach; oy < -reach + noff; ++oy) {
+                    const int qy = (cy + oy + nc) % nc;
+                    const int rowc = SJ.cell0 + (qz * nc + qy) * nc;  // cell (0, qy, qz)
+                    // pieces in list order: wrapped high end, main run, wrapped low end
+                    int s0 = 0, e0 = 0, s1 = 0, e1 = 0, s2 = 0, e2 = 0;
+                    if (real) {
+                        if (whole) {
+                            s1 = d.cell_start[rowc];
+                            e1 = d.cell_end[rowc + nc - 1];
+                        } else {
+                            const int a = cx - reach, b = cx + reach;
+                            if (a < 0) {
+                                s0 = d.cell_start[rowc + a + nc];
+                                e0 = d.cell_end[rowc + nc - 1];
+                            }
+                            s1 = d.cell_start[rowc + max(a, 0)];
+                            e1 = d.cell_end[rowc + min(b, nc - 1)];
+                            if (b >= nc) {
+                                s2 = d.cell_start[rowc];
+                                e2 = d.cell_end[rowc + b - nc];
+                            }
+                        }
                     }
+                    scan_staged(s0, e0);
+                    scan_staged(s1, e1);
+                    scan_staged(s2, e2);
                 }
             }
         }
