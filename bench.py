@@ -59,6 +59,9 @@ def parse():
     p.add_argument("--profile-steps", type=int, default=200)
     p.add_argument("--no-batch", action="store_true", help="skip the batched-replica leg")
     p.add_argument("--batch-steps", type=int, default=1000)
+    p.add_argument("--batch-large", action="store_true",
+                   help="also run the 64-replica batch (N 50k-500k each, ~17.6M particles) with admission, "
+                        "RDF and MSD sampling")
     p.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                    help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -224,6 +227,58 @@ def batched(md, torch, W, steps):
     return out
 
 
+def batched_large(md, torch, W):
+    """64 replicas, N uniform on [5e4, 5e5], density in {1.1, 1.2, 1.3}, T on
+    [0.45, 1.0], MIXED: admission against the free device memory, lattice
+    start, 1000 stochastic-bath steps, then 1000 NVE steps replayed from a
+    graph in four blocks of 250 with an RDF sample (r_max 5.0, 200 bins) and
+    an MSD origin at the start of each block.  The NVE steps are timed; the
+    RDF and MSD calls are timed on their own."""
+    wl = W.ka_batch_large()
+    reps_all = md.make_replicas([(r.n, r.n_a, r.box, r.temperature, r.seed) for r in wl.replicas])
+    cfg = md.make_config("mixed", wl.dt, 0.3, md.INIT_LATTICE)
+    free, _ = torch.cuda.mem_get_info()
+    adm, cnt = md.md_admit(cfg, reps_all, int(free * 0.8))
+    chosen = [r for r, a in zip(wl.replicas, adm) if a]
+    reps = [(r.n, r.n_a, r.box, r.temperature, r.seed) for r in chosen]
+    n_tot = sum(r.n for r in chosen)
+    t0 = time.perf_counter()
+    s = md.System(reps, precision="mixed", dt=wl.dt, skin=0.3, init="lattice", auto_sync=False)
+    log(f"batch-large init ({cnt} of {len(wl.replicas)} replicas admitted, {n_tot} particles) "
+        f"{time.perf_counter() - t0:.1f} s")
+    s.step_nvt(500, md.NVT_STOCHASTIC, n_reassign=10)
+    s.step_nvt(500, md.NVT_STOCHASTIC, n_reassign=50)
+    dr = 5.0 / 200
+    s.rdf(dr, 200)  # allocates the histogram grid (a reallocation would drop a captured graph)
+    s.stream.synchronize()
+    md.md_graph_capture(s.ctx, 250, 0)
+    obs0 = s.observables()
+    t_nve = t_rdf = t_msd = 0.0
+    for blk in range(4):
+        t1 = time.perf_counter()
+        s.msd_set_origin(blk)
+        s.rdf(dr, 200)
+        s.stream.synchronize()
+        t_rdf += time.perf_counter() - t1
+        t1 = time.perf_counter()
+        md.md_graph_launch(s.ctx)
+        s.stream.synchronize()
+        t_nve += time.perf_counter() - t1
+    t1 = time.perf_counter()
+    msd = [s.msd(k) for k in range(4)]
+    t_msd = time.perf_counter() - t1
+    obs1 = s.observables()
+    drift = np.abs(obs1[:, 4] - obs0[:, 4]) / np.abs(obs0[:, 4]) * (1e4 / 1000)
+    out = {"workload": wl.name, "n_replicas_admitted": cnt, "n_replicas": len(wl.replicas), "n_atoms": n_tot,
+           "precision": "mixed", "nve_steps": 1000, "value": n_tot * 1000 / t_nve, "unit": "atom-steps/s",
+           "ms_per_step": t_nve * 1e3 / 1000, "rdf_ms_per_sample": t_rdf * 1e3 / 4,
+           "msd_ms_per_measurement": t_msd * 1e3 / 4, "max_drift_per_1e4": float(drift.max()),
+           "median_drift_per_1e4": float(np.median(drift)),
+           "msd_A_after_1000_steps_median": float(np.median(msd[0][:, 0])), "device_error_word": s.status()}
+    s.close()
+    return out
+
+
 def calibrate_copy(torch, mib):
     n = mib * 1024 * 1024 // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -329,6 +384,12 @@ def main():
         log(f"batched: {batch}")
         torch.cuda.empty_cache()
 
+    batch_large = None
+    if a.batch_large:
+        batch_large = batched_large(md, torch, W)
+        log(f"batched large: {batch_large}")
+        torch.cuda.empty_cache()
+
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(wl, a.cpu_seconds)
@@ -357,6 +418,7 @@ def main():
         "fp64_gpu": fp64,
         "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
         "batched": batch,
+        "batched_large": batch_large,
         "cpu_baseline": cpu,
         "autotune": tune,
         "analysis": analysis,

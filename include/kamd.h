@@ -200,6 +200,14 @@ int md_rdf(kamd_ctx *ctx, double dr, int32_t n_bins, uint64_t *hist_dev);
  * `slot`. */
 int md_msd(kamd_ctx *ctx, int32_t op, int32_t slot, double *out_dev);
 
+/* Log-spaced measurement steps for the MSD (Sec. VI.B.1, Eqs.
+ * (logtimessteps), (A)): A = (n_md / t0)^(1/kmax), t_0 = t0, t_{k+1} = A t_k;
+ * the steps are the distinct values round(t_k) (round half to even) in
+ * [1, n_md], in increasing order.  Host only, no context.  Writes up to
+ * max_out steps to out (host, may be NULL when max_out is 0) and the total
+ * count to *count.  KAMD_EINVAL for n_md < 1, t0 < 0.5, kmax < 1. */
+int md_log_schedule(int32_t n_md, double t0, int32_t kmax, int32_t *out, int32_t max_out, int32_t *count);
+
 /* Current observables per replica into host_out (host, FP64 [n_rep][6]):
  * {KE, PE, W, T, E_tot, P} with KE = sum v^2/2, PE the shifted potential,
  * T = 2 KE / (3N) (Eq. (equip3N)), E_tot = KE + PE (Eq. (EsysNpart)) and

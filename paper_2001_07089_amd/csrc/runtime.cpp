@@ -1066,6 +1066,29 @@ extern "C" int md_set_state(kamd_ctx *c, const void *blob, size_t bytes)
     return maybe_export(c);
 }
 
+extern "C" int md_log_schedule(int32_t n_md, double t0, int32_t kmax, int32_t *out, int32_t max_out, int32_t *count)
+{
+    if (!count || n_md < 1 || !(t0 >= 0.5) || kmax < 1 || max_out < 0 || (max_out > 0 && !out))
+        return fail(nullptr, KAMD_EINVAL, "md_log_schedule: bad argument");
+    const double A = std::pow((double)n_md / t0, 1.0 / (double)kmax);
+    int32_t n = 0;
+    long prev = 0;
+    double t = t0;
+    for (int guard = 0; guard < 1 << 24; ++guard) {  // A > 1 unless n_md <= t0
+        const long s = (long)std::nearbyint(t);
+        if (s > n_md) break;
+        if (s != prev) {
+            if (n < max_out) out[n] = (int32_t)s;
+            ++n;
+            prev = s;
+        }
+        if (!(A > 1.0)) break;
+        t *= A;
+    }
+    *count = n;
+    return KAMD_OK;
+}
+
 extern "C" int md_autotune(kamd_ctx *c, int32_t probe_steps, double *host_out)
 {
     if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");

@@ -33,7 +33,8 @@ KA_RC_FACTOR = 2.5
 EXPORTED = ("md_workspace_size", "md_admit", "md_init", "md_build_cells", "md_forces", "md_step_nve",
             "md_step_nvt", "md_rdf", "md_msd", "md_observables", "md_thermostat_state", "md_sync",
             "md_import", "md_graph_capture", "md_graph_launch", "md_autotune", "md_set_list_params",
-            "md_stats", "md_get_state", "md_set_state", "md_profile", "md_status", "md_last_error", "md_destroy")
+            "md_stats", "md_get_state", "md_set_state", "md_profile", "md_status", "md_last_error", "md_destroy",
+            "md_log_schedule")
 
 
 class KamdError(RuntimeError):
@@ -97,6 +98,7 @@ def lib():
             "md_status": [P, C.POINTER(u32)],
             "md_profile": [P, i32, P],
             "md_destroy": [P],
+            "md_log_schedule": [i32, f64, i32, P, i32, C.POINTER(i32)],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -237,6 +239,15 @@ def md_autotune(ctx, probe_steps: int = 100):
     out = np.zeros(3)
     _check(lib().md_autotune(ctx, int(probe_steps), out.ctypes.data), ctx)
     return {"skin": float(out[0]), "cell_div": int(out[1]), "ms_per_step": float(out[2])}
+
+
+def md_log_schedule(n_md: int, t0: float = 1.0, kmax: int = 60):
+    """Log-spaced measurement steps (host only): numpy int32 array."""
+    cnt = C.c_int32(0)
+    _check(lib().md_log_schedule(int(n_md), float(t0), int(kmax), None, 0, C.byref(cnt)))
+    out = np.zeros(max(cnt.value, 1), np.int32)
+    _check(lib().md_log_schedule(int(n_md), float(t0), int(kmax), out.ctypes.data, int(cnt.value), C.byref(cnt)))
+    return out[:cnt.value]
 
 
 def md_set_list_params(ctx, skin: float, cell_div: int):

@@ -4,6 +4,8 @@ and admission logic behave as documented."""
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 from paper_2001_07089_amd import md
@@ -94,3 +96,23 @@ def test_missing_library_fails_loudly(monkeypatch):
     monkeypatch.setattr(md, "LIB_PATH", "/nonexistent/libkamd.so")
     with pytest.raises(RuntimeError):
         md.lib()
+
+
+def test_log_schedule_matches_oracle_and_definition():
+    """Host-side log schedule of the library against the oracle's loop (Sec.
+    VI.B.1) and against its definition: distinct, increasing, inside [1, n_md],
+    first step round(t0), last step n_md."""
+    import oracle as O
+    for n_md, t0, kmax in [(1000, 1.0, 60), (10000, 1.0, 60), (100000, 1.0, 60), (500, 2.5, 30),
+                           (7, 1.0, 10), (20000, 10.0, 40)]:
+        got = md.md_log_schedule(n_md, t0, kmax)
+        ref = O.log_schedule(n_md, t0, kmax)
+        assert np.array_equal(got, ref), (n_md, t0, kmax)
+        assert np.all(np.diff(got) > 0) and got[0] == round(t0) and got[-1] == n_md
+    assert len(md.md_log_schedule(1000, 1.0, 60)) == 50
+    # degenerate growth factor A = 1 (n_md == t0): the single step t0
+    assert list(md.md_log_schedule(1, 1.0, 5)) == [1]
+    with pytest.raises(md.KamdError):
+        md.md_log_schedule(0, 1.0, 60)
+    with pytest.raises(md.KamdError):
+        md.md_log_schedule(100, 0.2, 60)

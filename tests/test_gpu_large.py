@@ -152,3 +152,38 @@ def test_large_msd_closed_form():
     assert got[0] == pytest.approx(exp_a, rel=1e-12)
     assert got[1] == pytest.approx(6.25, rel=1e-12)
     s.close()
+
+
+def test_batch_large_three_densities_match_oracle():
+    """Replicas of the 64-replica workload (N 5e4-5e5, density 1.1 / 1.2 / 1.3):
+    the smallest replica of each density in one batch, mixed precision, forces
+    and potential energy per replica against the oracle's cell-list routine;
+    the whole workload fits the device by the admission planner."""
+    wl = W.ka_batch_large()
+    cfg = md.make_config("mixed", wl.dt, 0.3, md.INIT_LATTICE)
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    adm, cnt = md.md_admit(cfg, md.make_replicas([(r.n, r.n_a, r.box, r.temperature, r.seed)
+                                                  for r in wl.replicas]), int(free * 0.8))
+    log(f"case batch-large admission: {cnt} of {len(wl.replicas)}")
+    assert cnt == len(wl.replicas)
+    pick = []
+    for rho in (1.1, 1.2, 1.3):
+        cands = [r for r in wl.replicas if abs(r.rho - rho) < 1e-9]
+        pick.append(min(cands, key=lambda r: r.n))
+    log("case batch-large forces: " + ", ".join(f"n={r.n} rho={r.rho}" for r in pick))
+    pos = [W.lattice_config(r.n, r.box, r.seed, 0.1) for r in pick]
+    cat = [np.concatenate([p[k] for p in pos]) for k in range(3)]
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed) for r in pick], precision="mixed",
+                  positions=cat, skin=0.3)
+    obs = s.forces(energy=True)
+    a = s.numpy(("ax", "ay", "az"))
+    for i, r in enumerate(pick):
+        sl = s.replica_slice(i)
+        fx, fy, fz, pe, _ = O.forces(*pos[i], r.n_a, r.box, "cell")
+        err = normwise((a["ax"][sl], a["ay"][sl], a["az"][sl]), (fx, fy, fz))
+        log(f"  rho={r.rho} normwise {err:.3e}")
+        assert err <= 1e-5
+        assert obs[i, 0] == pytest.approx(pe, rel=1e-5)
+    assert s.status() == 0
+    s.close()
