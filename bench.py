@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--profile-steps", type=int, default=200)
     p.add_argument("--no-batch", action="store_true", help="skip the batched-replica leg")
     p.add_argument("--batch-steps", type=int, default=1000)
+    p.add_argument("--ladder", action="store_true",
+                   help="also run a temperature ladder: 64 independent N=1000 ladders through T = 3.0 ... 0.5")
     p.add_argument("--batch-large", action="store_true",
                    help="also run the 64-replica batch (N 50k-500k each, ~17.6M particles) with admission, "
                         "RDF and MSD sampling")
@@ -279,6 +281,31 @@ def batched_large(md, torch, W):
     return out
 
 
+def ladder_leg(md, W):
+    """64 independent ladders (replicas) of the paper's N = 1000, L = 9.41
+    system through T = 3.0, 2.0, 1.0, 0.8, 0.6, 0.55, 0.5: stochastic bath,
+    energy rescale, NVE equilibration, NVE production with log-spaced MSD and
+    a fit of D_A, D_B (mean over ladders).  Whole-sequence throughput."""
+    from paper_2001_07089_amd import ladder
+    wl = W.ka_small()
+    r0 = wl.replicas[0]
+    reps = [(r0.n, r0.n_a, r0.box, 3.0, r0.seed + 17 * k) for k in range(64)]
+    s = md.System(reps, precision="mixed_fixed", dt=wl.dt, skin=0.3, init="rsa", auto_sync=False)
+    s.step_nvt(500, md.NVT_STOCHASTIC, n_reassign=10)
+    stages = [ladder.Stage(T, 2000, 10000) for T in (3.0, 2.0, 1.0, 0.8, 0.6, 0.55, 0.5)]
+    t0 = time.perf_counter()
+    res = ladder.run_ladder(s, stages, wl.dt, rescale_energy=True)
+    el = time.perf_counter() - t0
+    steps = sum(2 * st.n_equil + st.n_prod for st in stages)
+    n_tot = 64 * r0.n
+    out = {"ladders": 64, "n_per_ladder": r0.n, "steps": steps, "value": n_tot * steps / el, "unit": "atom-steps/s",
+           "seconds": el, "D_A_B_by_T": {f"{r.temperature}": [float(x) for x in r.diffusion.mean(axis=0)]
+                                          for r in res},
+           "device_error_word": s.status()}
+    s.close()
+    return out
+
+
 def calibrate_copy(torch, mib):
     n = mib * 1024 * 1024 // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -384,6 +411,11 @@ def main():
         log(f"batched: {batch}")
         torch.cuda.empty_cache()
 
+    lad = None
+    if a.ladder:
+        lad = ladder_leg(md, W)
+        log(f"ladder: {lad}")
+
     batch_large = None
     if a.batch_large:
         batch_large = batched_large(md, torch, W)
@@ -419,6 +451,7 @@ def main():
         "speedup_vs_fp64_gpu": (value / fp64["value"]) if fp64 else None,
         "batched": batch,
         "batched_large": batch_large,
+        "ladder": lad,
         "cpu_baseline": cpu,
         "autotune": tune,
         "analysis": analysis,

@@ -200,6 +200,18 @@ int md_rdf(kamd_ctx *ctx, double dr, int32_t n_bins, uint64_t *hist_dev);
  * `slot`. */
 int md_msd(kamd_ctx *ctx, int32_t op, int32_t slot, double *out_dev);
 
+/* Change the bath temperature of every replica (host, FP64 [n_rep], each
+ * finite and > 0), as between the stages of a temperature ladder (Sec. V):
+ * later stochastic-bath redraws and Nose-Hoover calls use it (a Nose-Hoover
+ * call recomputes Q = 3 N T tau^2).  A captured Nose-Hoover graph keeps the Q
+ * of its capture.  Syncs. */
+int md_set_temperature(kamd_ctx *ctx, const double *temperature);
+
+/* Multiply every velocity of replica r by factor[r] (host, FP64 [n_rep],
+ * finite, >= 0), as for rescaling to a target total energy after a bath run
+ * (Sec. V; Appendix exercises).  Forces are unchanged.  Syncs. */
+int md_scale_velocities(kamd_ctx *ctx, const double *factor);
+
 /* Log-spaced measurement steps for the MSD (Sec. VI.B.1, Eqs.
  * (logtimessteps), (A)): A = (n_md / t0)^(1/kmax), t_0 = t0, t_{k+1} = A t_k;
  * the steps are the distinct values round(t_k) (round half to even) in

@@ -167,6 +167,7 @@ hipError_t launch_mb_draw(const Dev &d, uint32_t tag, hipStream_t s);
 hipError_t launch_mb_draw_dev(const Dev &d, hipStream_t s);
 hipError_t launch_mb_center(const Dev &d, hipStream_t s);
 hipError_t launch_mb_scale(const Dev &d, hipStream_t s);
+hipError_t launch_scale_v(const Dev &d, const double *f, hipStream_t s);
 hipError_t launch_ke_partial(const Dev &d, hipStream_t s);
 
 hipError_t launch_import(const Dev &d, const double *const *arr, const int32_t *img, hipStream_t s);

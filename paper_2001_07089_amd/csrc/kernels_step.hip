@@ -283,6 +283,17 @@ __global__ __launch_bounds__(BLOCK) void k_mb_scale(Dev d)
     d.vz[c.s] *= f;
 }
 
+// Velocities of every particle of replica r times f[r] (f: device, [nrep]).
+__global__ __launch_bounds__(BLOCK) void k_scale_v(Dev d, const double *f)
+{
+    SlotCtx c;
+    if (!slot_ctx(d, c) || !c.real) return;
+    const double a = f[c.rep];
+    d.vx[c.s] *= a;
+    d.vy[c.s] *= a;
+    d.vz[c.s] *= a;
+}
+
 // ------------------------------------------------------------- transfers
 struct Arr9 {
     const double *p[9];
@@ -440,6 +451,11 @@ hipError_t launch_mb_center(const Dev &d, hipStream_t s)
 hipError_t launch_mb_scale(const Dev &d, hipStream_t s)
 {
     hipLaunchKernelGGL(k_mb_scale, dim3(nblk(d)), dim3(BLOCK), 0, s, d);
+    return hipGetLastError();
+}
+hipError_t launch_scale_v(const Dev &d, const double *f, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scale_v, dim3(nblk(d)), dim3(BLOCK), 0, s, d, f);
     return hipGetLastError();
 }
 hipError_t launch_import(const Dev &d, const double *const *arr, const int32_t *img, hipStream_t s)

@@ -39,6 +39,7 @@ struct kamd_ctx {
     uint4 *mirror_alt = nullptr;      // second u32 mirror (fused force+drift steps)
     uint32_t *md_base = nullptr;      // [2][n_rep] displacement maxima
     double *Q_dev = nullptr;
+    double *rep_arg = nullptr;        // per-replica host arguments staged for a kernel
     double *obs_stage = nullptr;      // device [n_rep][4]
     double *state_tmp = nullptr;      // device caller-order staging for checkpoints
     int32_t *img_tmp = nullptr;
@@ -217,6 +218,7 @@ static size_t plan_bytes(const Plan &P, int n_rep)
     b += (8 + 4 + 32) * (size_t)P.nwaves;      // kmax, disp, wred
     b += (sizeof(SegInfo) + sizeof(RepInfo)) * 2 * (size_t)n_rep + 4 * (P.nwaves + P.ncells);
     b += 3 * 8 * nt;                           // one MSD origin (more on demand)
+    b += 8 * (size_t)n_rep;                    // per-replica kernel arguments
     return b;
 }
 
@@ -390,6 +392,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     TRY(dalloc(c, &d.err, 4));
     TRY(dalloc(c, &d.counters, 8));
     TRY(dalloc(c, &c->Q_dev, d.nrep));
+    TRY(dalloc(c, &c->rep_arg, d.nrep));
     TRY(dalloc(c, &c->obs_stage, 4 * (size_t)d.nrep));
     // zero everything that is read before written
     for (auto p : f64) HIPCHK(c, launch_zero_f64(*p, np, c->stream));
@@ -790,6 +793,34 @@ extern "C" int md_step_nvt(kamd_ctx *c, int32_t nsteps, int32_t mode, int32_t n_
     if (nsteps == 0) return KAMD_OK;
     TRY(enqueue_steps(c, nsteps, 1, mode, n_reassign, false));
     c->step += nsteps;
+    return maybe_export(c);
+}
+
+extern "C" int md_set_temperature(kamd_ctx *c, const double *temperature)
+{
+    if (!c || !temperature) return fail(c, KAMD_EINVAL, "null argument");
+    for (size_t r = 0; r < c->reps.size(); ++r)
+        if (!(temperature[r] > 0.0) || !std::isfinite(temperature[r]))
+            return fail(c, KAMD_EINVAL, "temperature of replica %zu must be finite and > 0", r);
+    for (size_t r = 0; r < c->reps.size(); ++r) {
+        c->reps[r].temperature = temperature[r];
+        c->rinfo[r].T = temperature[r];
+    }
+    HIPCHK(c, hipMemcpyAsync((void *)c->d.rep, c->rinfo.data(), sizeof(RepInfo) * c->rinfo.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return KAMD_OK;
+}
+
+extern "C" int md_scale_velocities(kamd_ctx *c, const double *factor)
+{
+    if (!c || !factor) return fail(c, KAMD_EINVAL, "null argument");
+    for (size_t r = 0; r < c->reps.size(); ++r)
+        if (!(factor[r] >= 0.0) || !std::isfinite(factor[r]))
+            return fail(c, KAMD_EINVAL, "velocity factor of replica %zu must be finite and >= 0", r);
+    HIPCHK(c, hipMemcpyAsync(c->rep_arg, factor, 8 * c->reps.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, launch_scale_v(c->d, c->rep_arg, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));  // the host array may go away after the call
     return maybe_export(c);
 }
 

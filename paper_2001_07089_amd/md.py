@@ -34,7 +34,7 @@ EXPORTED = ("md_workspace_size", "md_admit", "md_init", "md_build_cells", "md_fo
             "md_step_nvt", "md_rdf", "md_msd", "md_observables", "md_thermostat_state", "md_sync",
             "md_import", "md_graph_capture", "md_graph_launch", "md_autotune", "md_set_list_params",
             "md_stats", "md_get_state", "md_set_state", "md_profile", "md_status", "md_last_error", "md_destroy",
-            "md_log_schedule")
+            "md_log_schedule", "md_set_temperature", "md_scale_velocities")
 
 
 class KamdError(RuntimeError):
@@ -99,6 +99,8 @@ def lib():
             "md_profile": [P, i32, P],
             "md_destroy": [P],
             "md_log_schedule": [i32, f64, i32, P, i32, C.POINTER(i32)],
+            "md_set_temperature": [P, P],
+            "md_scale_velocities": [P, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -241,6 +243,16 @@ def md_autotune(ctx, probe_steps: int = 100):
     return {"skin": float(out[0]), "cell_div": int(out[1]), "ms_per_step": float(out[2])}
 
 
+def md_set_temperature(ctx, temperatures):
+    t = np.ascontiguousarray(temperatures, np.float64)
+    _check(lib().md_set_temperature(ctx, t.ctypes.data), ctx)
+
+
+def md_scale_velocities(ctx, factors):
+    f = np.ascontiguousarray(factors, np.float64)
+    _check(lib().md_scale_velocities(ctx, f.ctypes.data), ctx)
+
+
 def md_log_schedule(n_md: int, t0: float = 1.0, kmax: int = 60):
     """Log-spaced measurement steps (host only): numpy int32 array."""
     cnt = C.c_int32(0)
@@ -370,6 +382,15 @@ class System:
         out = self._zeros((self.n_rep, 2), self.torch.float64)
         md_msd(self.ctx, 1, slot, out.data_ptr())
         return self._host(out)
+
+    def set_temperature(self, temperatures):
+        """Bath temperature per replica (scalar or sequence)."""
+        t = np.broadcast_to(np.asarray(temperatures, np.float64), (self.n_rep,)).copy()
+        md_set_temperature(self.ctx, t)
+
+    def scale_velocities(self, factors):
+        f = np.broadcast_to(np.asarray(factors, np.float64), (self.n_rep,)).copy()
+        md_scale_velocities(self.ctx, f)
 
     def observables(self):
         return md_observables(self.ctx, self.n_rep)

@@ -371,3 +371,72 @@ def test_autotune_picks_a_valid_skin():
     s.step_nve(50)
     assert s.status() == 0
     s.close()
+
+
+def test_set_temperature_redraw_and_nose_hoover_match_oracle():
+    """md_set_temperature: the next bath redraw is the oracle's flow chart at
+    the new temperature, and a Nose-Hoover run afterwards uses Q = 3 N T tau^2
+    at the new T (oracle recurrence, same start)."""
+    n, T0, T1 = 1500, 0.2, 0.65
+    log("case set temperature")
+    s = system([(n, T0, 14, 1.2)], "fp64")
+    s.set_temperature(T1)
+    s.step_nvt(10, md.NVT_STOCHASTIC, n_reassign=10)
+    a = s.numpy()
+    vx, vy, vz = O.mb_velocities(n, T1, 1000 + 14, rep=0, tag=10)
+    assert np.max(np.abs(a["vx"] - vx)) < 1e-12 and np.max(np.abs(a["vz"] - vz)) < 1e-12
+    s.close()
+    x, y, z, vx, vy, vz, na, L = relaxed(n, 1.0, 15)
+    s = md.System([(n, na, L, 1.0, 1)], precision="fp64", positions=(x, y, z), velocities=(vx, vy, vz))
+    s.set_temperature(0.7)
+    st = O.State(x, y, z, vx, vy, vz, na, L)
+    st.compute_forces()
+    tau = 0.5
+    O.run_nh(st, 0.005, 20, 0.7, 3 * n * 0.7 * tau ** 2)
+    s.step_nvt(20, md.NVT_NOSE_HOOVER, tau=tau)
+    th = md.md_thermostat_state(s.ctx, 1)[0]
+    assert th[0] == pytest.approx(st.xi, rel=1e-9, abs=1e-12)
+    assert th[1] == pytest.approx(st.lns, rel=1e-9, abs=1e-12)
+    with pytest.raises(md.KamdError):
+        s.set_temperature(-1.0)
+    s.close()
+
+
+def test_scale_velocities_per_replica():
+    log("case scale velocities")
+    s = system([(800, 1.0, 21, 1.2), (1200, 0.6, 22, 1.2)], "fp64")
+    a0 = s.numpy()
+    o0 = s.observables()
+    f = np.array([1.25, 0.5])
+    s.scale_velocities(f)
+    a1 = s.numpy()
+    o1 = s.observables()
+    for i in range(2):
+        sl = s.replica_slice(i)
+        for k in ("vx", "vy", "vz"):
+            assert np.array_equal(a1[k][sl], a0[k][sl] * f[i])
+        for k in ("x", "ax"):
+            assert np.array_equal(a1[k][sl], a0[k][sl])
+    assert np.allclose(o1[:, 0], o0[:, 0] * f ** 2, rtol=1e-13)
+    assert np.array_equal(o1[:, 1], o0[:, 1])
+    s.close()
+
+
+def test_temperature_ladder_end_to_end():
+    """Four independent ladders (replicas) through T = 2.0 and 1.0 with energy
+    rescaling: the MSD grows,
+    D decreases with T, and B particles diffuse faster than A (Sec. V)."""
+    from paper_2001_07089_amd import ladder
+    log("case temperature ladder")
+    s = system([(1000, 2.0, 31 + r, 1.2) for r in range(4)], "mixed_fixed")
+    stages = [ladder.Stage(2.0, 400, 3000), ladder.Stage(1.0, 400, 3000)]
+    res = ladder.run_ladder(s, stages, 0.005, rescale_energy=True)
+    for r in res:
+        assert np.all(np.diff(r.msd[:, :, 0], axis=0)[-10:] > 0)
+        assert np.all(r.diffusion > 0)
+    d2, d1 = res[0].diffusion.mean(axis=0), res[1].diffusion.mean(axis=0)
+    log(f"  D(2.0) = {d2}, D(1.0) = {d1}")
+    assert d2[0] > d1[0] and d2[1] > d1[1]
+    assert d1[1] > d1[0]
+    assert s.status() == 0
+    s.close()
