@@ -200,6 +200,15 @@ int md_rdf(kamd_ctx *ctx, double dr, int32_t n_bins, uint64_t *hist_dev);
  * `slot`. */
 int md_msd(kamd_ctx *ctx, int32_t op, int32_t slot, double *out_dev);
 
+/* Self part of the van Hove correlation function (the time generalisation
+ * of g(r) named at the end of Sec. VI.A; definition of Hansen and McDonald):
+ * adds to hist_dev (device, uint64 [n_rep][2][n_bins], A row then B row;
+ * accumulated, the caller zeroes it) the count of particles whose unwrapped
+ * displacement r = |r_u - r_u(origin slot)| has int(r / dr) = bin < n_bins.
+ * The origin is set with md_msd(SET_ORIGIN).  KAMD_EINVAL for a slot outside
+ * [0, 16), dr < 1e-6 or n_bins outside [1, 1024].  Asynchronous. */
+int md_van_hove(kamd_ctx *ctx, int32_t slot, double dr, int32_t n_bins, uint64_t *hist_dev);
+
 /* Change the bath temperature of every replica (host, FP64 [n_rep], each
  * finite and > 0), as between the stages of a temperature ladder (Sec. V):
  * later stochastic-bath redraws and Nose-Hoover calls use it (a Nose-Hoover

@@ -87,6 +87,9 @@ def lib():
         L.ora_rdf_hist.restype = None
         L.ora_msd.argtypes = [C.c_int, C.c_int, C.c_double, _D, _D, _D, _I32, _D, _D, _D, _D]
         L.ora_msd.restype = None
+        L.ora_van_hove_self.argtypes = [C.c_int, C.c_int, C.c_double, _D, _D, _D, _I32, _D, _D, _D,
+                                        C.c_double, C.c_int, _U64]
+        L.ora_van_hove_self.restype = None
         L.ora_log_schedule.argtypes = [C.c_int, C.c_double, C.c_int, _I32, C.c_int]
         L.ora_log_schedule.restype = C.c_int
         L.ora_num_threads.argtypes = []
@@ -261,6 +264,16 @@ def msd(x, y, z, img, na, L, x0u, y0u, z0u):
     x, y, z = _c(x), _c(y), _c(z)
     lib().ora_msd(x.size, int(na), float(L), x, y, z, _c(img, np.int32), _c(x0u), _c(y0u),
                   _c(z0u), out)
+    return out
+
+
+def van_hove_self(x, y, z, img, na, L, x0u, y0u, z0u, dr, nbins):
+    """Self van Hove histogram per species ([2][nbins] uint64) of the unwrapped
+    displacements against an unwrapped origin."""
+    out = np.zeros((2, int(nbins)), np.uint64)
+    x, y, z = _c(x), _c(y), _c(z)
+    lib().ora_van_hove_self(x.size, int(na), float(L), x, y, z, _c(img, np.int32), _c(x0u), _c(y0u), _c(z0u),
+                            float(dr), int(nbins), out)
     return out
 
 

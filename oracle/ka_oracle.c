@@ -542,6 +542,29 @@ void ora_msd(int n, int na, double L, const double *x, const double *y,
     out[1] = n - na > 0 ? sb / (double)(n - na) : 0.0;
 }
 
+/* Self part of the van Hove correlation function, the time generalisation
+ * of g(r) named at the end of Sec. VI.A (definition of Hansen and McDonald,
+ * as used by Kob and Andersen): per species, the histogram over particles of
+ * the distance r = |r_u(t) - r_u(t_w)| between the unwrapped position and the
+ * unwrapped origin, bin = int(r / dr), counted when bin < nbins.  Normalised
+ * to G_s(r, t) by the caller (divide by N_a and the shell volume).
+ * out: [2][nbins] counts, accumulated. */
+void ora_van_hove_self(int n, int na, double L, const double *x, const double *y,
+                       const double *z, const int32_t *img, const double *x0,
+                       const double *y0, const double *z0, double dr, int nbins,
+                       uint64_t *out)
+{
+    for (int i = 0; i < n; ++i) {
+        double ux = x[i] + (double)img[i] * L;
+        double uy = y[i] + (double)img[n + i] * L;
+        double uz = z[i] + (double)img[2 * n + i] * L;
+        double dx = ux - x0[i], dy = uy - y0[i], dz = uz - z0[i];
+        double r = sqrt(dx * dx + dy * dy + dz * dz);
+        int bin = (int)(r / dr);
+        if (bin < nbins) out[(size_t)(i < na ? 0 : 1) * nbins + bin] += 1u;
+    }
+}
+
 /* Logarithmically spaced measurement steps (Sec. VI.B.1,
  * Eqs. (logtimessteps),(A)): A = (nMD / t0)^(1/kmax); the next measurement
  * step is the nearest integer to t0 A^k (ties to even), advancing k while the

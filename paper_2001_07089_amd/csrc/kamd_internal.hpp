@@ -22,6 +22,7 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;               // threads per block for slot kernels
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 constexpr int LIST_ROW_ALIGN = 4;        // neighbour rows are padded to this multiple
+constexpr int VH_MAX_BINS = 1024;       // bins of the self van Hove histogram
 constexpr int LIST_UNROLL = 8;           // candidates per step of the list builder's scan
 
 // Neighbour-list layout.  The list of wavefront w is a block of rows * 64
@@ -183,5 +184,6 @@ hipError_t launch_rdf(const Dev &d, double dr, int nbins, int nblocks, uint64_t 
 hipError_t launch_msd_set(const Dev &d, int slot, hipStream_t s);
 hipError_t launch_msd_measure(const Dev &d, int slot, hipStream_t s);
 hipError_t launch_msd_finish(const Dev &d, double *out, hipStream_t s);
+hipError_t launch_van_hove(const Dev &d, int slot, double dr, int nbins, uint64_t *hist, hipStream_t s);
 
 }  // namespace kamd

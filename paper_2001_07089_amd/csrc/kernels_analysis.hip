@@ -174,6 +174,41 @@ __global__ __launch_bounds__(BLOCK) void k_msd_measure(Dev d, int slot)
     }
 }
 
+// Self part of the van Hove function: per replica and species, the histogram
+// of |r_u - r_u(origin)| over particles, bin = int(r / dr) kept when
+// < n_bins.  Per-wave u32 histograms in LDS (a wave holds one replica and one
+// type), flushed to the uint64 result [n_rep][2][n_bins].
+__global__ __launch_bounds__(BLOCK) void k_van_hove(Dev d, int slot, double dr, int nbins, uint64_t *hist)
+{
+    __shared__ uint32_t lh[WAVES_PER_BLOCK][VH_MAX_BINS];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int w = blockIdx.x * WAVES_PER_BLOCK + wv;
+    if (w >= d.nwaves) return;  // per-wave work, no block barrier below
+    uint32_t *h = lh[wv];
+    for (int b = lane; b < nbins; b += WAVE) h[b] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const SegInfo &S = d.seg[d.wave_seg[w]];
+    const int s = w * WAVE + lane;
+    if (s - S.slot0 < S.n) {
+        const double L = d.rep[S.rep].L;
+        const int np = d.npad_total;
+        const int g = d.id[s];
+        const double *o = d.origin + (size_t)slot * 3 * d.n_total;
+        const double dx = d.x[s] + (double)d.img[s] * L - o[g];
+        const double dy = d.y[s] + (double)d.img[np + s] * L - o[d.n_total + g];
+        const double dz = d.z[s] + (double)d.img[2 * np + s] * L - o[2 * d.n_total + g];
+        const double r = sqrt(dx * dx + dy * dy + dz * dz);
+        const int bin = (int)(r / dr);
+        if (bin < nbins) atomicAdd(&h[bin], 1u);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint64_t *out = hist + ((size_t)S.rep * 2 + S.type) * nbins;
+    for (int b = lane; b < nbins; b += WAVE)
+        if (h[b]) atomicAdd((unsigned long long *)&out[b], (unsigned long long)h[b]);
+}
+
 __global__ void k_msd_finish(Dev d, double *out)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,6 +244,12 @@ hipError_t launch_msd_set(const Dev &d, int slot, hipStream_t s)
 hipError_t launch_msd_measure(const Dev &d, int slot, hipStream_t s)
 {
     hipLaunchKernelGGL(k_msd_measure, dim3(nblk(d)), dim3(BLOCK), 0, s, d, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_van_hove(const Dev &d, int slot, double dr, int nbins, uint64_t *hist, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_van_hove, dim3(nblk(d)), dim3(BLOCK), 0, s, d, slot, dr, nbins, hist);
     return hipGetLastError();
 }
 

@@ -882,6 +882,16 @@ extern "C" int md_msd(kamd_ctx *c, int32_t op, int32_t slot, double *out_dev)
     return KAMD_OK;
 }
 
+extern "C" int md_van_hove(kamd_ctx *c, int32_t slot, double dr, int32_t n_bins, uint64_t *hist_dev)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (slot < 0 || slot >= 16) return fail(c, KAMD_EINVAL, "origin slot must be in [0, 16)");
+    if (!(dr >= 1e-6) || !std::isfinite(dr) || n_bins <= 0 || n_bins > VH_MAX_BINS || !hist_dev)
+        return fail(c, KAMD_EINVAL, "bad van Hove arguments (dr >= 1e-6, 0 < n_bins <= %d)", VH_MAX_BINS);
+    HIPCHK(c, launch_van_hove(c->d, slot, dr, n_bins, hist_dev, c->stream));
+    return KAMD_OK;
+}
+
 extern "C" int md_observables(kamd_ctx *c, double *host_out)
 {
     if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");

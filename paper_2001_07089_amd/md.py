@@ -34,7 +34,7 @@ EXPORTED = ("md_workspace_size", "md_admit", "md_init", "md_build_cells", "md_fo
             "md_step_nvt", "md_rdf", "md_msd", "md_observables", "md_thermostat_state", "md_sync",
             "md_import", "md_graph_capture", "md_graph_launch", "md_autotune", "md_set_list_params",
             "md_stats", "md_get_state", "md_set_state", "md_profile", "md_status", "md_last_error", "md_destroy",
-            "md_log_schedule", "md_set_temperature", "md_scale_velocities")
+            "md_log_schedule", "md_set_temperature", "md_scale_velocities", "md_van_hove")
 
 
 class KamdError(RuntimeError):
@@ -100,6 +100,7 @@ def lib():
             "md_destroy": [P],
             "md_log_schedule": [i32, f64, i32, P, i32, C.POINTER(i32)],
             "md_set_temperature": [P, P],
+            "md_van_hove": [P, i32, f64, i32, P],
             "md_scale_velocities": [P, P],
         }
         for name, args in sig.items():
@@ -243,6 +244,10 @@ def md_autotune(ctx, probe_steps: int = 100):
     return {"skin": float(out[0]), "cell_div": int(out[1]), "ms_per_step": float(out[2])}
 
 
+def md_van_hove(ctx, slot: int, dr: float, n_bins: int, hist_ptr: int):
+    _check(lib().md_van_hove(ctx, int(slot), float(dr), int(n_bins), hist_ptr), ctx)
+
+
 def md_set_temperature(ctx, temperatures):
     t = np.ascontiguousarray(temperatures, np.float64)
     _check(lib().md_set_temperature(ctx, t.ctypes.data), ctx)
@@ -382,6 +387,14 @@ class System:
         out = self._zeros((self.n_rep, 2), self.torch.float64)
         md_msd(self.ctx, 1, slot, out.data_ptr())
         return self._host(out)
+
+    def van_hove(self, slot, dr, n_bins, hist=None):
+        """Self van Hove histogram against MSD origin `slot`: int64 tensor
+        [n_rep][2][n_bins] (accumulated into `hist` when given)."""
+        if hist is None:
+            hist = self._zeros((self.n_rep, 2, n_bins), self.torch.int64)
+        md_van_hove(self.ctx, slot, dr, n_bins, hist.data_ptr())
+        return hist
 
     def set_temperature(self, temperatures):
         """Bath temperature per replica (scalar or sequence)."""

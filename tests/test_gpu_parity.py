@@ -440,3 +440,55 @@ def test_temperature_ladder_end_to_end():
     assert d1[1] > d1[0]
     assert s.status() == 0
     s.close()
+
+
+def test_van_hove_self_matches_oracle_bit_exact():
+    """Self van Hove histogram against an MSD origin, two replicas, FP64:
+    counts equal the oracle's for every bin."""
+    log("case van hove")
+    cfgs = [(1200, 1.0, 41, 1.2), (800, 0.8, 42, 1.2)]
+    s = system(cfgs, "fp64")
+    a0 = s.numpy(("x", "y", "z"))
+    img0 = s.images()
+    s.msd_set_origin(2)
+    s.step_nve(60)
+    a = s.numpy(("x", "y", "z"))
+    img = s.images()
+    dr, nb = 0.01, 400
+    h = s._host(s.van_hove(2, dr, nb)).astype(np.uint64)
+    for i, (n, T, seed, rho) in enumerate(cfgs):
+        sl = s.replica_slice(i)
+        L = W.box_for(n, rho)
+        na = W.n_a_for(n)
+        u0 = O.unwrapped(a0["x"][sl], a0["y"][sl], a0["z"][sl], img0[:, sl], L)
+        ref = O.van_hove_self(a["x"][sl], a["y"][sl], a["z"][sl], np.ascontiguousarray(img[:, sl]), na, L,
+                              *u0, dr, nb)
+        assert np.array_equal(h[i], ref), i
+        assert int(h[i][0].sum()) == na and int(h[i][1].sum()) == n - na
+    with pytest.raises(md.KamdError):
+        s.van_hove(2, dr, 5000)
+    s.close()
+
+
+def test_quench_aging_two_time_msd():
+    """Instant quench T = 2.0 -> 0.3: younger systems move more over the same
+    lag (two-time MSD, Eq. (msdtw)); the van Hove histograms at each point
+    hold every particle."""
+    from paper_2001_07089_amd import aging
+    log("case quench aging")
+    s = system([(1000, 2.0, 51 + r, 1.2) for r in range(4)], "mixed_fixed")
+    out = aging.quench(s, 0.3, 1000, t_w=(0, 10, 100, 500), van_hove=(0.02, 1024))
+    def at(tw, lag):
+        k = int(np.searchsorted(out[tw].lags, lag))
+        assert out[tw].lags[k] == lag
+        return out[tw].msd[k].mean(axis=0)
+    common = np.intersect1d(out[0].lags, out[500].lags)  # the two schedules differ (n_MD differs)
+    lag = int(common[np.argmin(np.abs(common - 100))])
+    m0, m500 = at(0, lag), at(500, lag)
+    log(f"  msd(t_w=0, lag {lag}) = {m0}, msd(t_w=500) = {m500}")
+    assert m0[0] > m500[0] and m0[1] > m500[1]
+    vh = out[10].van_hove
+    assert vh.shape[1:] == (4, 2, 1024)
+    assert np.all(vh[:, :, 0, :].sum(axis=-1) == W.n_a_for(1000))
+    assert s.status() == 0
+    s.close()

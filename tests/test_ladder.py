@@ -85,3 +85,33 @@ def test_run_ladder_without_rescale_keeps_velocities():
     assert [r.temperature for r in out] == [2.0, 1.0]
     assert not any(c[0] == "scale" for c in fs.calls)
     assert [c for c in fs.calls if c[0] == "T"] == [("T", 2.0), ("T", 1.0)]
+
+
+class FakeAgingSystem(FakeSystem):
+    def __init__(self):
+        super().__init__(1, ke=[1.0], pe=[-6.0], e_series=[])
+        self.origins = {}
+
+    def msd_set_origin(self, slot):
+        self.calls.append(("origin", slot, self.t))
+        self.origins[slot] = self.t
+
+    def msd(self, slot):
+        return np.array([[float(self.t - self.origins[slot]), 0.0]])
+
+
+def test_quench_schedule_per_waiting_time():
+    from paper_2001_07089_amd import aging
+    fs = FakeAgingSystem()
+    out = aging.quench(fs, 0.3, 1000, t_w=(0, 10, 100, 500))
+    assert fs.calls[0] == ("T", 0.3)
+    origins = [c for c in fs.calls if c[0] == "origin"]
+    assert [(c[1], c[2]) for c in origins] == [(0, 0), (1, 10), (2, 100), (3, 500)]
+    assert sum(c[1] for c in fs.calls if c[0] == "nvt") == 1000
+    for tw, cur in out.items():
+        assert np.array_equal(cur.lags, md.md_log_schedule(1000 - tw, 1.0, 60))
+        # each recorded value is the lag itself (the stand-in's MSD is t - t_origin)
+        assert np.array_equal(cur.msd[:, 0, 0], cur.lags.astype(float))
+    import pytest as _pt
+    with _pt.raises(ValueError):
+        aging.quench(fs, 0.3, 100, t_w=(0, 100))

@@ -442,3 +442,30 @@ def test_log_schedule_closed_form():
         assert s[-1] == nmd
     s = O.log_schedule(1000, 1.0, 60)
     assert len(s) == 50 and s[:11].tolist() == list(range(1, 12))
+
+
+def test_van_hove_self_closed_form():
+    """Self van Hove histogram: A particles displaced by one common vector all
+    land in the bin of its length, B particles by another; a displacement that
+    crosses the box several times counts through the image counters; lengths
+    at or past n_bins * dr are not counted."""
+    n, na, L = 50, 40, 6.0
+    rng = np.random.default_rng(3)
+    x0, y0, z0 = (rng.uniform(0, L, n) for _ in range(3))
+    img0 = np.zeros((3, n), np.int32)
+    ux0, uy0, uz0 = O.unwrapped(x0, y0, z0, img0, L)
+    shA, shB = np.array([0.31, -0.4, 1.2]), np.array([2.0 * L + 0.52, 0.0, 0.0])  # lengths off bin edges
+    shift = np.where(np.arange(n)[None, :] < na, shA[:, None], shB[:, None])
+    u = np.array([x0, y0, z0]) + shift
+    img = np.floor(u / L).astype(np.int32)
+    w = u - img * L
+    dr = 0.05
+    h = O.van_hove_self(w[0], w[1], w[2], img, na, L, ux0, uy0, uz0, dr, 400)
+    binA, binB = int(np.linalg.norm(shA) / dr), int(np.linalg.norm(shB) / dr)
+    assert h[0, binA] == na and h[0].sum() == na
+    assert h[1, binB] == n - na and h[1].sum() == n - na
+    h2 = O.van_hove_self(w[0], w[1], w[2], img, na, L, ux0, uy0, uz0, dr, binB)  # B beyond the range
+    assert h2[1].sum() == 0 and h2[0].sum() == na
+    # MSD of the same configuration is the squared common length per species
+    m = O.msd(w[0], w[1], w[2], img, na, L, ux0, uy0, uz0)
+    assert m[0] == pytest.approx(shA @ shA, rel=1e-12) and m[1] == pytest.approx(shB @ shB, rel=1e-12)
