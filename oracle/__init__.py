@@ -74,11 +74,14 @@ def lib():
         L.ora_mb_velocities.argtypes = [C.c_int, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32,
                                         C.c_void_p, _D, _D, _D]
         L.ora_mb_velocities.restype = None
-        L.ora_run.argtypes = [MP, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
+        L.ora_mb_velocities_d.argtypes = [C.c_int, C.c_int, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32,
+                                          C.c_void_p, _D, _D, _D]
+        L.ora_mb_velocities_d.restype = None
+        L.ora_run.argtypes = [MP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
                               C.c_int64, _D, _D, _D, _D, _D, _D, _D, _D, _D, _I32,
                               C.c_int, C.c_double, C.c_uint64, C.c_uint32, C.c_void_p, C.c_void_p]
         L.ora_run.restype = None
-        L.ora_run_nh.argtypes = [MP, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
+        L.ora_run_nh.argtypes = [MP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int,
                                  C.c_double, C.c_double, C.c_int,
                                  _D, _D, _D, _D, _D, _D, _D, _D, _D, _I32, _D, C.c_void_p]
         L.ora_run_nh.restype = None
@@ -152,12 +155,13 @@ def gauss3(seed: int, rep: int, tag: int, pid: int):
     return g
 
 
-def mb_velocities(n: int, T: float, seed: int, rep: int = 0, tag: int = 0, ids=None):
-    """Maxwell-Boltzmann flow chart of Sec. II.E.1 with Philox Gaussians."""
+def mb_velocities(n: int, T: float, seed: int, rep: int = 0, tag: int = 0, ids=None, dim: int = 3):
+    """Maxwell-Boltzmann flow chart of Sec. II.E.1 with Philox Gaussians
+    (dim 2: planar, vz = 0, sum v^2 = 2 N T)."""
     vx, vy, vz = np.empty(n), np.empty(n), np.empty(n)
     ids_arr = None if ids is None else _c(ids, np.int32)
-    lib().ora_mb_velocities(int(n), float(T), int(seed), int(rep), int(tag),
-                            None if ids_arr is None else ids_arr.ctypes.data, vx, vy, vz)
+    lib().ora_mb_velocities_d(int(dim), int(n), float(T), int(seed), int(rep), int(tag),
+                              None if ids_arr is None else ids_arr.ctypes.data, vx, vy, vz)
     return vx, vy, vz
 
 
@@ -189,7 +193,7 @@ class State:
 
 
 def run(st: State, dt: float, nsteps: int, method: str = "cell", m: Model = None,
-        step0: int = 0, nb: int = 0, T: float = 0.0, seed: int = 0, rep: int = 0, ids=None):
+        step0: int = 0, nb: int = 0, T: float = 0.0, seed: int = 0, rep: int = 0, ids=None, dim: int = 3):
     """Velocity-Verlet NVE steps (optionally with the stochastic bath every nb steps).
 
     st.ax.. must hold the forces of the entry positions.  Returns an array
@@ -198,7 +202,7 @@ def run(st: State, dt: float, nsteps: int, method: str = "cell", m: Model = None
     m = m or model()
     e = np.zeros((nsteps, 3))
     ids_arr = None if ids is None else _c(ids, np.int32)
-    lib().ora_run(C.byref(m), 1 if method == "cell" else 0, st.n, st.na, st.L, float(dt),
+    lib().ora_run(C.byref(m), 1 if method == "cell" else 0, int(dim), st.n, st.na, st.L, float(dt),
                   int(nsteps), int(step0), st.x, st.y, st.z, st.vx, st.vy, st.vz,
                   st.ax, st.ay, st.az, st.img, int(nb), float(T), int(seed), int(rep),
                   None if ids_arr is None else ids_arr.ctypes.data, e.ctypes.data)
@@ -206,7 +210,7 @@ def run(st: State, dt: float, nsteps: int, method: str = "cell", m: Model = None
 
 
 def run_nh(st: State, dt: float, nsteps: int, T: float, Q: float, method: str = "cell",
-           m: Model = None, exact_solve: bool = False):
+           m: Model = None, exact_solve: bool = False, dim: int = 3):
     """Nose-Hoover steps (Fox-Andersen scheme of Appendix B).
 
     Returns (nsteps, 5) of {KE, PE, W, xi, ln s} after each step.
@@ -214,7 +218,7 @@ def run_nh(st: State, dt: float, nsteps: int, T: float, Q: float, method: str = 
     m = m or model()
     e = np.zeros((nsteps, 5))
     nh = np.array([st.xi, st.lns])
-    lib().ora_run_nh(C.byref(m), 1 if method == "cell" else 0, st.n, st.na, st.L, float(dt),
+    lib().ora_run_nh(C.byref(m), 1 if method == "cell" else 0, int(dim), st.n, st.na, st.L, float(dt),
                      int(nsteps), float(T), float(Q), 1 if exact_solve else 0,
                      st.x, st.y, st.z, st.vx, st.vy, st.vz, st.ax, st.ay, st.az, st.img,
                      nh, e.ctypes.data)
@@ -222,10 +226,10 @@ def run_nh(st: State, dt: float, nsteps: int, T: float, Q: float, method: str = 
     return e
 
 
-def nh_conserved(e_row, n, T, Q):
-    """Eq. (HNosetilde): KE + PE + Q xi^2 / 2 + X T ln s with X = 3N."""
+def nh_conserved(e_row, n, T, Q, dim: int = 3):
+    """Eq. (HNosetilde): KE + PE + Q xi^2 / 2 + X T ln s with X = d N."""
     ke, pe, _, xi, lns = e_row
-    return ke + pe + 0.5 * Q * xi * xi + 3.0 * n * T * lns
+    return ke + pe + 0.5 * Q * xi * xi + float(dim) * n * T * lns
 
 
 def rdf_hist(x, y, z, na, L, dr, nbins, hist=None):
@@ -236,21 +240,25 @@ def rdf_hist(x, y, z, na, L, dr, nbins, hist=None):
     return h
 
 
-def rdf_normalize(hist, n, na, L, dr, nmeas):
+def rdf_normalize(hist, n, na, L, dr, nmeas, dim: int = 3):
     """g_AA, g_AB, g_BB at bin mid-points (Eqs. (gAA),(gAB); normalisation of Sec. VI.A.1).
 
-    Shell volume (4 pi / 3)(r_out^3 - r_in^3), V = L^3, nmeas measurements.
-    Returns (r_mid, g) with g rows AA, AB, BB.
+    Shell volume (4 pi / 3)(r_out^3 - r_in^3) and V = L^3; for the planar
+    system (dim 2, the appendix exercise) the shell area pi (r_out^2 - r_in^2)
+    and V = L^2.  nmeas measurements.  Returns (r_mid, g), rows AA, AB, BB.
     """
     nb = n - na
     nbins = hist.shape[1]
     g = np.zeros((3, nbins))
     rmid = np.zeros(nbins)
-    V = L ** 3
+    V = L ** dim
     for b in range(nbins):
         rin = b * dr
         rout = rin + dr
-        shell = (4.0 * math.pi / 3.0) * (rout ** 3 - rin ** 3)
+        if dim == 2:
+            shell = math.pi * (rout ** 2 - rin ** 2)
+        else:
+            shell = (4.0 * math.pi / 3.0) * (rout ** 3 - rin ** 3)
         g[0, b] = (V / (na * (na - 1))) * float(hist[0, b]) / (shell * nmeas) if na > 1 else 0.0
         g[1, b] = (V / (na * nb)) * float(hist[1, b]) / (shell * nmeas) if na > 0 and nb > 0 else 0.0
         g[2, b] = (V / (nb * (nb - 1))) * float(hist[2, b]) / (shell * nmeas) if nb > 1 else 0.0

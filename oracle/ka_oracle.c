@@ -354,11 +354,12 @@ void ora_gauss3(uint64_t seed, uint32_t rep, uint32_t tag, uint32_t id, double g
  * of the flow chart in Sec. II.E.1: (1) Gaussian components with standard
  * deviation sqrt(kT/m), Eqs. (vxocitydistribution),(sigmavx); (2) mass
  * scaling (m = 1, nothing to do); (3) subtract the centre-of-mass velocity;
- * (4) rescale so that sum v^2 = 3 N T exactly (Eq. (equip3N)).
+ * (4) rescale so that sum v^2 = d N T exactly (Eq. (equip3N), with 3
+ * replaced by d for the planar system of the appendix, which keeps vz = 0).
  * ids[i] is the counter word identifying particle i (its index in the
- * caller's order); NULL means ids[i] = i. */
-void ora_mb_velocities(int n, double T, uint64_t seed, uint32_t rep, uint32_t tag,
-                       const int32_t *ids, double *vx, double *vy, double *vz)
+ * caller's order); NULL means ids[i] = i.  dim is 3 or 2. */
+void ora_mb_velocities_d(int dim, int n, double T, uint64_t seed, uint32_t rep, uint32_t tag,
+                         const int32_t *ids, double *vx, double *vy, double *vz)
 {
     double sig = sqrt(T);
     for (int i = 0; i < n; ++i) {
@@ -366,7 +367,7 @@ void ora_mb_velocities(int n, double T, uint64_t seed, uint32_t rep, uint32_t ta
         ora_gauss3(seed, rep, tag, ids ? (uint32_t)ids[i] : (uint32_t)i, g);
         vx[i] = sig * g[0];
         vy[i] = sig * g[1];
-        vz[i] = sig * g[2];
+        vz[i] = dim == 2 ? 0.0 : sig * g[2];
     }
     double sx = 0.0, sy = 0.0, sz = 0.0;
     for (int i = 0; i < n; ++i) { sx += vx[i]; sy += vy[i]; sz += vz[i]; }
@@ -374,8 +375,14 @@ void ora_mb_velocities(int n, double T, uint64_t seed, uint32_t rep, uint32_t ta
     for (int i = 0; i < n; ++i) { vx[i] -= sx; vy[i] -= sy; vz[i] -= sz; }
     double s2 = 0.0;
     for (int i = 0; i < n; ++i) s2 += vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
-    double scale = sqrt(3.0 * T * (double)n / s2);
+    double scale = sqrt((double)dim * T * (double)n / s2);
     for (int i = 0; i < n; ++i) { vx[i] *= scale; vy[i] *= scale; vz[i] *= scale; }
+}
+
+void ora_mb_velocities(int n, double T, uint64_t seed, uint32_t rep, uint32_t tag,
+                       const int32_t *ids, double *vx, double *vy, double *vz)
+{
+    ora_mb_velocities_d(3, n, T, seed, rep, tag, ids, vx, vy, vz);
 }
 
 /* Velocity-Verlet NVE steps in the order of the time loop of Sec. III.E:
@@ -384,9 +391,10 @@ void ora_mb_velocities(int n, double T, uint64_t seed, uint32_t rep, uint32_t ta
  * On entry a must hold the forces of the entry positions.
  * Optional stochastic bath (Sec. III.G): after step s (s counted from
  * step0 + 1), when nb > 0 and s % nb == 0, all velocities are redrawn by
- * ora_mb_velocities with draw tag s.
+ * ora_mb_velocities_d (dimension dim) with draw tag s.  A planar system
+ * (dim 2, z = vz = 0 on entry) stays planar: its forces have no z part.
  * energy_out (may be NULL) receives, per step, {KE, PE, W} after the step. */
-void ora_run(const ora_model *m, int use_cell, int n, int na, double L, double dt,
+void ora_run(const ora_model *m, int use_cell, int dim, int n, int na, double L, double dt,
              int nsteps, int64_t step0,
              double *x, double *y, double *z, double *vx, double *vy, double *vz,
              double *ax, double *ay, double *az, int32_t *img,
@@ -415,7 +423,7 @@ void ora_run(const ora_model *m, int use_cell, int n, int na, double L, double d
         }
         int64_t step = step0 + s;
         if (nb > 0 && step % nb == 0)
-            ora_mb_velocities(n, T, seed, rep, (uint32_t)step, ids, vx, vy, vz);
+            ora_mb_velocities_d(dim, n, T, seed, rep, (uint32_t)step, ids, vx, vy, vz);
         if (energy_out) {
             energy_out[3 * (s - 1) + 0] = ora_kinetic(n, vx, vy, vz);
             energy_out[3 * (s - 1) + 1] = pe;
@@ -425,7 +433,7 @@ void ora_run(const ora_model *m, int use_cell, int n, int na, double L, double d
 }
 
 /* Nose-Hoover steps with the Fox-Andersen velocity-Verlet scheme of
- * Appendix B (m = 1, X = 3N, k_B = 1).  Per step, with K = sum v(t)^2 and
+ * Appendix B (m = 1, X = d N with d = dim, k_B = 1).  Per step, with K = sum v(t)^2 and
  * G = (K - X T) / Q:
  *   r(t+dt)  = r + v dt + (a - xi v) dt^2 / 2         Eq. (Noseupdate_ri),
  *              read with the velocity where the text prints the position;
@@ -442,14 +450,14 @@ void ora_run(const ora_model *m, int use_cell, int n, int na, double L, double d
  * Eq. (ridotsolved) instead (used by tests to compare the two forms).
  * nh_state = {xi, ln_s} is updated in place.
  * energy_out (may be NULL) receives per step {KE, PE, W, xi, ln_s}. */
-void ora_run_nh(const ora_model *m, int use_cell, int n, int na, double L, double dt,
+void ora_run_nh(const ora_model *m, int use_cell, int dim, int n, int na, double L, double dt,
                 int nsteps, double T, double Q, int exact_solve,
                 double *x, double *y, double *z, double *vx, double *vy, double *vz,
                 double *ax, double *ay, double *az, int32_t *img,
                 double *nh_state, double *energy_out)
 {
     double xi = nh_state[0], lns = nh_state[1];
-    double X = 3.0 * (double)n;
+    double X = (double)dim * (double)n;  /* degrees of freedom, X = dN */
     double dt2 = dt * dt;
     double *bx = (double *)malloc(sizeof(double) * (size_t)n);
     double *by = (double *)malloc(sizeof(double) * (size_t)n);

@@ -469,3 +469,98 @@ def test_van_hove_self_closed_form():
     # MSD of the same configuration is the squared common length per species
     m = O.msd(w[0], w[1], w[2], img, na, L, ux0, uy0, uz0)
     assert m[0] == pytest.approx(shA @ shA, rel=1e-12) and m[1] == pytest.approx(shB @ shB, rel=1e-12)
+
+
+_PLANAR = {}
+
+
+def _planar_liquid(n=400, seed=7, T=0.6):
+    """Planar 65:35 KA system at N/L^2 = 1.204 (appendix exercise), z = vz = 0,
+    relaxed with the planar bath (a copy of a cached state)."""
+    key = (n, seed, T)
+    if key not in _PLANAR:
+        _PLANAR[key] = _make_planar(n, seed, T)
+    st = _PLANAR[key]
+    c = O.State(st.x, st.y, st.z, st.vx, st.vy, st.vz, st.na, st.L)
+    c.compute_forces("brute")
+    return c
+
+
+def _make_planar(n, seed, T):
+    L = math.sqrt(n / 1.204)
+    na = int(round(0.65 * n))
+    m = int(math.ceil(math.sqrt(n)))
+    a = L / m
+    rng = np.random.default_rng(seed)
+    sites = rng.permutation(m * m)[:n]
+    x = (sites % m + 0.5 + rng.uniform(-0.05, 0.05, n)) * a
+    y = (sites // m + 0.5 + rng.uniform(-0.05, 0.05, n)) * a
+    z = np.zeros(n)
+    vx, vy, vz = O.mb_velocities(n, T, 99, dim=2)
+    st = O.State(x % L, y % L, z, vx, vy, vz, na, L)
+    st.compute_forces("brute")
+    O.run(st, 0.00025, 300, method="brute", nb=5, T=T, seed=99, dim=2)
+    O.run(st, 0.002, 3000, method="brute", nb=10, T=T, seed=99, dim=2, step0=300)
+    return st
+
+
+def test_planar_maxwell_boltzmann_draw():
+    """Planar flow chart: vz = 0, zero momentum, sum v^2 = 2 N T exactly, and
+    (x, y) are the three-dimensional draw's first two Gaussians recentred and
+    rescaled (one common factor)."""
+    n, T = 500, 0.7
+    vx2, vy2, vz2 = O.mb_velocities(n, T, 11, rep=3, tag=20, dim=2)
+    vx3, vy3, _ = O.mb_velocities(n, T, 11, rep=3, tag=20)
+    assert np.all(vz2 == 0.0)
+    assert abs(vx2.sum()) < 1e-12 and abs(vy2.sum()) < 1e-12
+    assert np.sum(vx2 ** 2 + vy2 ** 2) == pytest.approx(2 * n * T, rel=1e-13)
+    ratio = vx2 / vx3
+    assert np.allclose(ratio, ratio[0], rtol=1e-12) and np.allclose(vy2 / vy3, ratio[0], rtol=1e-12)
+
+
+def test_planar_system_stays_planar_and_conserves_energy():
+    st = _planar_liquid()
+    assert np.all(st.z == 0.0) and np.all(st.vz == 0.0) and np.all(st.az == 0.0)
+    e = O.run(st, 0.001, 300, method="brute")
+    tot = e[:, 0] + e[:, 1]
+    assert np.all(st.z == 0.0) and np.all(st.img[2] == 0)
+    assert np.max(np.abs(tot - tot[0])) / abs(tot[0]) < 1e-4
+
+
+def test_planar_nose_hoover_conserves_with_2n_degrees():
+    """Planar Nose-Hoover: the extended energy with X = 2N is conserved; with
+    X = 3N (the three-dimensional count) it drifts, so the oracle's X follows
+    the dimension."""
+    st = _planar_liquid()
+    n, T, tau = st.n, 0.4, 0.2
+    Q = 2 * n * T * tau ** 2
+    e = O.run_nh(st, 0.001, 400, T, Q, method="brute", dim=2)
+    h2 = np.array([O.nh_conserved(r, n, T, Q, dim=2) for r in e])
+    h3 = np.array([O.nh_conserved(r, n, T, Q, dim=3) for r in e])
+    d2 = np.max(np.abs(h2 - h2[0])) / abs(h2[0])
+    d3 = np.max(np.abs(h3 - h3[0])) / abs(h3[0])
+    assert d2 < 2e-4 and d3 > 100 * d2
+
+
+def test_planar_square_lattice_rdf():
+    """Pair histogram of a perfect square lattice (all A): the neighbour
+    shells of the square lattice per particle (AA counts 2 per pair, so a
+    shell of k neighbours holds k N counts); the planar normalisation turns
+    the first shell into a coordination number of exactly 4."""
+    m = 20
+    a = 1.13  # a, a*sqrt(2), 2a all lie well inside their bins of width 0.05
+    L = m * a
+    n = m * m
+    i = np.arange(n)
+    x, y, z = (i % m + 0.5) * a, (i // m + 0.5) * a, np.zeros(n)
+    dr = 0.05
+    h = O.rdf_hist(x, y, z, n, L, dr, 60)
+    # within r_max = 3.0: 4 at a, 4 at a*sqrt(2), 4 at 2a, 8 at a*sqrt(5)
+    for r, k in ((a, 4), (a * math.sqrt(2), 4), (2 * a, 4), (a * math.sqrt(5), 8)):
+        assert h[0, int(r / dr)] == k * n
+    assert int(h[0].sum()) == 20 * n
+    rmid, g = O.rdf_normalize(h, n, n, L, dr, 1, dim=2)
+    rho = n / L ** 2
+    b = int(a / dr)
+    shell = math.pi * (((b + 1) * dr) ** 2 - (b * dr) ** 2)
+    assert rho * g[0, b] * shell * (n - 1) / n == pytest.approx(4.0, rel=1e-12)
