@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--profile-steps", type=int, default=200)
     p.add_argument("--no-batch", action="store_true", help="skip the batched-replica leg")
     p.add_argument("--batch-steps", type=int, default=1000)
+    p.add_argument("--planar", action="store_true",
+                   help="also run the planar KA variant (65:35, N/L^2 = 1.204) at N = 2^20, T = 0.4")
     p.add_argument("--ladder", action="store_true",
                    help="also run a temperature ladder: 64 independent N=1000 ladders through T = 3.0 ... 0.5")
     p.add_argument("--batch-large", action="store_true",
@@ -281,6 +283,25 @@ def batched_large(md, torch, W):
     return out
 
 
+def planar_leg(md, torch, W, steps=1000):
+    """The planar KA variant of the appendix exercise at N = 2^20: square
+    lattice start, bath at T = 0.4, then graph-replayed NVE steps timed."""
+    wl = W.ka_planar(1 << 20, 0.4)
+    r = wl.replicas[0]
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision="mixed_fixed", dt=wl.dt, skin=0.3,
+                  init="lattice", auto_sync=False, dim=2)
+    s.step_nvt(500, md.NVT_STOCHASTIC, n_reassign=10)
+    s.step_nvt(1500, md.NVT_STOCHASTIC, n_reassign=50)
+    tune = md.md_autotune(s.ctx, 100)
+    s.step_nve(200)
+    el, e0, e1 = timed_graph(s, md, torch, steps)
+    out = {"workload": wl.name, "n_atoms": r.n, "box": r.box, "value": r.n * steps / el, "unit": "atom-steps/s",
+           "ms_per_step": el * 1e3 / steps, "drift_per_1e4": abs(e1 - e0) / abs(e0) * (1e4 / steps),
+           "autotune": tune, "device_error_word": s.status()}
+    s.close()
+    return out
+
+
 def ladder_leg(md, W):
     """64 independent ladders (replicas) of the paper's N = 1000, L = 9.41
     system through T = 3.0, 2.0, 1.0, 0.8, 0.6, 0.55, 0.5: stochastic bath,
@@ -411,6 +432,12 @@ def main():
         log(f"batched: {batch}")
         torch.cuda.empty_cache()
 
+    planar = None
+    if a.planar:
+        planar = planar_leg(md, torch, W)
+        log(f"planar: {planar}")
+        torch.cuda.empty_cache()
+
     lad = None
     if a.ladder:
         lad = ladder_leg(md, W)
@@ -452,6 +479,7 @@ def main():
         "batched": batch,
         "batched_large": batch_large,
         "ladder": lad,
+        "planar": planar,
         "cpu_baseline": cpu,
         "autotune": tune,
         "analysis": analysis,

@@ -124,6 +124,11 @@ typedef struct {
     double list_capacity;   /* neighbour-list rows as a multiple of the expected
                                count (0 = 1.6)                                      */
     int32_t auto_sync;      /* 1: export state to the caller arrays after every call */
+    int32_t dim;            /* 3 (or 0): three-dimensional; 2: the planar system of
+                               the appendix exercise, every z, vz and az is 0, the
+                               box is L x L at number density N/L^2, the bath and
+                               temperature use 2N degrees of freedom, pressure
+                               uses the area                                      */
 } kamd_config;
 
 /* Device bytes md_init would allocate for this configuration (host call, no

@@ -45,7 +45,7 @@ struct SegInfo {
     int32_t n;      // particles
     int32_t npad;   // slots (multiple of WAVE)
     int32_t cell0;  // first cell of this segment's list grid
-    int32_t ncell;  // nc^3
+    int32_t ncell;  // nc^3 (planar: nc^2)
     int32_t pad_;
 };
 
@@ -133,6 +133,7 @@ struct Dev {
     int32_t n_total;
     int32_t nwaves;
     int32_t nrep;
+    int32_t dim;          // 3, or 2 for a planar system (z = vz = 0)
     int32_t ncells;
     int32_t rows;         // neighbour-list row capacity
 };

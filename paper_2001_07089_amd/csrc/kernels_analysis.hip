@@ -12,9 +12,9 @@
 
 namespace kamd {
 
-// RDF grid: per replica rdf_nc^3 cells of edge L/rdf_nc >= n_bins*dr, both
-// particle types together.  Counting sort into rdf_pos (replica-relative
-// positions, w = type + 2*cell).
+// RDF grid: per replica rdf_nc^3 cells (a planar system: one layer of
+// rdf_nc^2) of edge L/rdf_nc >= n_bins*dr, both particle types together.
+// Counting sort into rdf_pos (replica-relative positions, w = type + 2*cell).
 __global__ __launch_bounds__(BLOCK) void k_rdf_assign(Dev d)
 {
     const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
@@ -25,7 +25,8 @@ __global__ __launch_bounds__(BLOCK) void k_rdf_assign(Dev d)
     const RepInfo &R = d.rep[S.rep];
     const int nc = R.rdf_nc;
     const uint4 m = d.mirror[s];
-    const int c = R.rdf_cell0 + (fix_cell(m.z, nc) * nc + fix_cell(m.y, nc)) * nc + fix_cell(m.x, nc);
+    const int cz = d.dim == 2 ? 0 : fix_cell(m.z, nc);
+    const int c = R.rdf_cell0 + (cz * nc + fix_cell(m.y, nc)) * nc + fix_cell(m.x, nc);
     d.rdf_cell_of[s] = c;
     d.rdf_rank[s] = atomicAdd(&d.rdf_count[c], 1);
 }
@@ -99,8 +100,9 @@ __global__ __launch_bounds__(BLOCK) void k_rdf_hist(Dev d, double dr, int nbins,
         const int nc = R.rdf_nc;
         const int cx = cl % nc, cy = (cl / nc) % nc, cz = cl / (nc * nc);
         const int noff = min(nc, 3);
+        const int oz0 = d.dim == 2 ? 0 : -1, nz = d.dim == 2 ? 1 : noff;  // planar: one layer
         const double L = R.L, half = 0.5 * R.L;
-        for (int oz = -1; oz < -1 + noff; ++oz) {
+        for (int oz = oz0; oz < oz0 + nz; ++oz) {
             const int qz = (cz + oz + nc) % nc;
             for (int oy = -1; oy < -1 + noff; ++oy) {
                 const int qy = (cy + oy + nc) % nc;

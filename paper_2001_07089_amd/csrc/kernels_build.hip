@@ -5,7 +5,8 @@
 // neighbour list as the optimisation it leaves out (end of Sec. III.E); its
 // LAMMPS runs use a binned list with a skin and a rebuild check every step
 // (Sec. IV, "neighbor 0.3 bin" with "check yes").  Here each replica has a
-// cubic grid of nc^3 cells of edge L/nc >= (largest cutoff + skin)/cell_div,
+// cubic grid of nc^3 cells of edge L/nc >= (largest cutoff + skin)/cell_div
+// (a planar system, whose particles all sit at z = 0, a single layer of nc^2),
 // and each particle keeps the list of all partners within r_c(ab) + skin,
 // rebuilt when some particle of the replica has moved more than skin/2 since
 // the last build (so no pair can enter the cutoff unseen).
@@ -53,7 +54,8 @@ __device__ inline void assign_wave(const Dev &d, int w)
     int c = -1 - lane;  // distinct dummy for padding lanes
     if (real) {
         const uint4 m = d.mirror[s];
-        c = S.cell0 + (fix_cell(m.z, nc) * nc + fix_cell(m.y, nc)) * nc + fix_cell(m.x, nc);
+        const int cz = d.dim == 2 ? 0 : fix_cell(m.z, nc);  // planar: one layer of cells
+        c = S.cell0 + (cz * nc + fix_cell(m.y, nc)) * nc + fix_cell(m.x, nc);
         d.cell_of[s] = c;
     }
     // Runs of consecutive lanes with the same cell (the slots are still in the
@@ -196,8 +198,8 @@ __device__ inline void sortgather_cell(const Dev &d, int c)
 __global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
 {
     if (d.rb_any[0] == 0) return;
-    const int c = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    if (c < d.ncells) sortgather_cell(d, c);
+    const int stride = gridDim.x * WAVES_PER_BLOCK;
+    for (int c = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); c < d.ncells; c += stride) sortgather_cell(d, c);
 }
 
 // Neighbour lists.  One thread per particle.  Entries [0, kA) of a list hold
@@ -285,7 +287,9 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     const int noff = min(nc, 2 * reach + 1);
     const bool whole = nc < 2 * reach + 1;  // every cell of a row is in the stencil
     const bool prune = !whole && reach > 1;
-    const int cx = fix_cell(mi.x, nc), cy = fix_cell(mi.y, nc), cz = fix_cell(mi.z, nc);
+    const int cx = fix_cell(mi.x, nc), cy = fix_cell(mi.y, nc), cz = d.dim == 2 ? 0 : fix_cell(mi.z, nc);
+    // a planar system has every particle in its single (z = 0) layer of cells
+    const int oz0 = d.dim == 2 ? 0 : -reach, nz = d.dim == 2 ? 1 : noff;
     const double cw = 4294967296.0 / (double)nc;  // cell edge in fixed units
     const double ux = (double)mi.x, uy = (double)mi.y, uz = (double)mi.z;
     int32_t *col = d.nbr + list_index(w, d.rows, 0, lane);
@@ -366,7 +370,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         };
         if (SJ.n > 0 && prune) {  // finer cells: per-particle pruning, direct scans
             if (real) {
-                for (int oz = -reach; oz < -reach + noff; ++oz) {
+                for (int oz = oz0; oz < oz0 + nz; ++oz) {
                     const double gz = fmax(gap(oz, cz, cw, uz), 0.0);
                     const int qz = (cz + oz + nc) % nc;
                     for (int oy = -reach; oy < -reach + noff; ++oy) {
@@ -400,7 +404,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                 }
             }
         } else if (SJ.n > 0) {  // every lane walks the same rows: staged scans
-            for (int oz = -reach; oz < -reach + noff; ++oz) {
+            for (int oz = oz0; oz < oz0 + nz; ++oz) {
                 const int qz = (cz + oz + nc) % nc;
                 for (int oy = -reach; oy < -reach + noff; ++oy) {
                     const int qy = (cy + oy + nc) % nc;
@@ -459,6 +463,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
 
 static inline int nblk_slots(const Dev &d) { return (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
 constexpr int CHAIN_MAX_BLOCKS = 1024;  // grid cap of the grid-stride chain kernels
+constexpr int SORT_MAX_BLOCKS = 1 << 16;  // grid cap of the per-cell sort-gather
 static inline int nblk_capped(int waves) { return std::min((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, CHAIN_MAX_BLOCKS); }
 
 hipError_t launch_rb_gate(const Dev &d, hipStream_t s)
@@ -483,7 +488,9 @@ hipError_t launch_rb_scatter(const Dev &d, hipStream_t s)
 }
 hipError_t launch_rb_sortgather(const Dev &d, hipStream_t s)
 {
-    const int nb = (d.ncells + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    // one wavefront per cell, over a grid capped well inside the 2^32
+    // work-item limit of a launch dimension (larger grids walk with a stride)
+    const int nb = std::min((d.ncells + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, SORT_MAX_BLOCKS);
     hipLaunchKernelGGL(k_rb_sortgather, dim3(nb), dim3(BLOCK), 0, s, d);
     return hipGetLastError();
 }

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void k_rep_reduce(Dev d, int mask)
 }
 
 // Nose-Hoover scalars before the drift (Appendix B): with K = sum v(t)^2,
-// G = (K - 3 N T) / Q: ln s += xi dt + G dt^2/2 (Eq. (Noseupdate_lns)),
+// G = (K - d N T) / Q: ln s += xi dt + G dt^2/2 (Eq. (Noseupdate_lns)),
 // xi_a = xi + G dt (Eq. (Noseupdate_xiapprox)), c = dt/2 (1 - dt/2 xi_a).
 __global__ void k_nh_begin(Dev d, double dt, const double *Q)
 {
@@ -135,7 +135,7 @@ __global__ void k_nh_begin(Dev d, double dt, const double *Q)
     if (r >= d.nrep) return;
     const RepInfo &R = d.rep[r];
     RepDyn &D = d.dyn[r];
-    const double X = 3.0 * (double)R.n;
+    const double X = (double)d.dim * (double)R.n;  // degrees of freedom d N
     const double G = (D.K2 - X * R.T) / Q[r];
     D.lns += D.xi * dt + 0.5 * G * dt * dt;
     D.xia = D.xi + G * dt;
@@ -150,7 +150,7 @@ __global__ void k_nh_end(Dev d, double dt, const double *Q)
     if (r >= d.nrep) return;
     const RepInfo &R = d.rep[r];
     RepDyn &D = d.dyn[r];
-    const double X = 3.0 * (double)R.n;
+    const double X = (double)d.dim * (double)R.n;  // degrees of freedom d N
     const double K1 = d.rsum[4 * r + 0];
     const double G = (D.K2 - X * R.T) / Q[r];
     const double G1 = (K1 - X * R.T) / Q[r];
@@ -238,7 +238,7 @@ __global__ __launch_bounds__(BLOCK) void k_mb_draw(Dev d, uint32_t tag, int tag_
         double g[3];
         gauss3(R.seed, (uint32_t)c.rep, tag, local, g);
         const double sg = sqrt(R.T);
-        sv[0] = sg * g[0]; sv[1] = sg * g[1]; sv[2] = sg * g[2];
+        sv[0] = sg * g[0]; sv[1] = sg * g[1]; sv[2] = d.dim == 2 ? 0.0 : sg * g[2];
         d.vx[c.s] = sv[0]; d.vy[c.s] = sv[1]; d.vz[c.s] = sv[2];
     }
 #pragma unroll
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(BLOCK) void k_mb_scale(Dev d)
     if (!slot_ctx(d, c)) return;
     if (!c.real) return;
     const RepInfo &R = d.rep[c.rep];
-    const double f = sqrt(3.0 * R.T * (double)R.n / d.rsum[4 * c.rep + 0]);
+    const double f = sqrt((double)d.dim * R.T * (double)R.n / d.rsum[4 * c.rep + 0]);
     d.vx[c.s] *= f;
     d.vy[c.s] *= f;
     d.vz[c.s] *= f;
@@ -317,6 +317,12 @@ __global__ __launch_bounds__(BLOCK) void k_import(Dev d, Arr9 a, const int32_t *
             if (k < 3) v = wrap_img(v, R.L, R.invL, im[k]);
             dst[k][s] = v;
         }
+    if (d.dim == 2) {  // planar: z, vz and az are zero by definition
+        d.z[s] = 0.0;
+        d.vz[s] = 0.0;
+        d.az[s] = 0.0;
+        im[2] = 0;
+    }
     d.img[s] = im[0]; d.img[np + s] = im[1]; d.img[2 * np + s] = im[2];
     d.mirror[s] = make_uint4(to_fix(d.x[s], R.invL), to_fix(d.y[s], R.invL), to_fix(d.z[s], R.invL), 0u);
 }

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -90,12 +91,15 @@ static void model_from(const kamd_model &m, Model &out, double &rc_max)
     }
 }
 
+static inline int dim_of(const kamd_config *cfg) { return cfg->dim == 2 ? 2 : 3; }
+
 static int validate(kamd_ctx *c, const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep)
 {
     if (!cfg || !reps || n_rep <= 0) return fail(c, KAMD_EINVAL, "null config/replicas or n_rep <= 0");
     if (cfg->precision < 0 || cfg->precision > 2) return fail(c, KAMD_EINVAL, "bad precision %d", cfg->precision);
     if (!(cfg->dt > 0.0)) return fail(c, KAMD_EINVAL, "dt must be > 0");
     if (cfg->cell_div < 0 || cfg->cell_div > 2) return fail(c, KAMD_EINVAL, "cell_div must be 0, 1 or 2");
+    if (cfg->dim != 0 && cfg->dim != 2 && cfg->dim != 3) return fail(c, KAMD_EINVAL, "dim must be 0, 2 or 3");
     if (!(cfg->model.rc_factor > 0.0)) return fail(c, KAMD_EINVAL, "rc_factor must be > 0");
     for (int p = 0; p < 3; ++p)
         if (!(cfg->model.sigma[p] > 0.0) || !std::isfinite(cfg->model.eps[p]))
@@ -122,7 +126,17 @@ struct Plan {
     std::vector<RepInfo> rinfo;
     std::vector<int32_t> wave_seg, cell_seg;
     int32_t npad = 0, nwaves = 0, ncells = 0, rows = 0, n_total = 0;
+    int64_t ncells_wide = 0;  // the same count without 32-bit truncation
 };
+
+// Limits of the list cell grid.  A segment holds at most 2^24 cells (nc is
+// lowered to fit: wider cells stay correct, they only add candidates), and a
+// plan at most 2^28 cells in all, which keeps every cell index, scan offset
+// and launch size far inside 32 bits.
+constexpr int64_t MAX_SEG_CELLS = (int64_t)1 << 24;
+constexpr int64_t MAX_PLAN_CELLS = (int64_t)1 << 28;
+
+static int cell_cap(int dim) { return dim == 2 ? 4096 : 256; }  // nc^(dim) <= MAX_SEG_CELLS
 
 static double list_skin(const kamd_config *cfg) { return cfg->skin < 0.0 ? 0.3 : cfg->skin; }
 
@@ -136,6 +150,15 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
     const double rlist = rcmax + skin;
     const double cap = cfg->list_capacity > 0.0 ? cfg->list_capacity : 1.6;
     P = Plan();
+    const bool planar = dim_of(cfg) == 2;
+    auto cells_per_edge = [&](double box) {
+        return (int)std::max(1.0, std::min(std::floor(box * reach / rlist), (double)cell_cap(dim_of(cfg))));
+    };
+    for (int r = 0; r < n_rep; ++r) {  // the grid size first: an oversize plan builds no cell table
+        const int64_t nc = cells_per_edge(reps[r].box);
+        P.ncells_wide += 2 * (planar ? nc * nc : nc * nc * nc);
+    }
+    const bool fits = P.ncells_wide <= MAX_PLAN_CELLS;
     int32_t slot = 0, cell = 0;
     double rows_need = 0.0;
     for (int r = 0; r < n_rep; ++r) {
@@ -152,8 +175,7 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
         R.skin = skin;
         const double half = 0.5 * skin;
         R.disp_thr2 = half * half * (1.0 - 1e-5);
-        int nc = (int)std::floor(K.box * reach / rlist);
-        nc = std::max(1, std::min(nc, 1024));
+        const int nc = cells_per_edge(K.box);
         R.nc = nc;
         const double h = K.box / 4294967296.0;
         for (int p = 0; p < 3; ++p) {
@@ -176,21 +198,26 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
             S.n = t == 0 ? K.n_a : K.n - K.n_a;
             S.npad = (S.n + WAVE - 1) / WAVE * WAVE;
             S.cell0 = cell;
-            S.ncell = nc * nc * nc;
+            // a planar system keeps every particle at z = 0: one layer of cells
+            S.ncell = planar ? nc * nc : nc * nc * nc;
             R.seg[t] = (int32_t)P.segs.size();
             for (int w = 0; w < S.npad / WAVE; ++w) P.wave_seg.push_back(R.seg[t]);
-            for (int c = 0; c < S.ncell; ++c) P.cell_seg.push_back(R.seg[t]);
+            if (fits) P.cell_seg.insert(P.cell_seg.end(), (size_t)S.ncell, R.seg[t]);
             slot += S.npad;
-            cell += S.ncell;
+            cell += fits ? S.ncell : 0;
             P.segs.push_back(S);
         }
         R.wave1 = slot / WAVE;
         P.rinfo.push_back(R);
         // expected list rows: wavefront maxima of the A part and the B part
-        const double V = K.box * K.box * K.box;
+        // (planar: number density per area, disc area)
+        const double V = planar ? K.box * K.box : K.box * K.box * K.box;
         const double rhoA = K.n_a / V, rhoB = (K.n - K.n_a) / V;
         const double pi43 = 4.0 / 3.0 * M_PI;
-        auto vol = [&](int p) { double rl = cfg->model.rc_factor * cfg->model.sigma[p] + skin; return pi43 * rl * rl * rl; };
+        auto vol = [&](int p) {
+            double rl = cfg->model.rc_factor * cfg->model.sigma[p] + skin;
+            return planar ? M_PI * rl * rl : pi43 * rl * rl * rl;
+        };
         const double rowsA = std::max(K.n_a > 0 ? rhoA * vol(0) + rhoB * vol(1) : 0.0,
                                       K.n > K.n_a ? rhoA * vol(1) + rhoB * vol(2) : 0.0);
         rows_need = std::max(rows_need, rowsA);
@@ -204,6 +231,14 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
     P.rows = rows;
 }
 
+static int plan_fits(kamd_ctx *c, const Plan &P)
+{
+    if (P.ncells_wide > MAX_PLAN_CELLS)
+        return fail(c, KAMD_EINVAL, "list cell grid of %lld cells exceeds the limit of %lld (fewer or smaller replicas)",
+                    (long long)P.ncells_wide, (long long)MAX_PLAN_CELLS);
+    return KAMD_OK;
+}
+
 // Bytes of device memory for a plan.
 static size_t plan_bytes(const Plan &P, int n_rep)
 {
@@ -213,10 +248,10 @@ static size_t plan_bytes(const Plan &P, int n_rep)
     b += 16 * np + 16 * LIST_UNROLL;           // mbuild, tail of the sorted mirror
     b += 4 * np * 3;                           // cell_of, rank, order
     b += 4 * np;                               // nlen
-    b += 4 * (size_t)P.ncells * 2;             // count/start
+    b += 4 * (size_t)P.ncells_wide * 3;        // count/start/end
     b += 4 * (size_t)P.rows * np;              // neighbour list
     b += (8 + 4 + 32) * (size_t)P.nwaves;      // kmax, disp, wred
-    b += (sizeof(SegInfo) + sizeof(RepInfo)) * 2 * (size_t)n_rep + 4 * (P.nwaves + P.ncells);
+    b += (sizeof(SegInfo) + sizeof(RepInfo)) * 2 * (size_t)n_rep + 4 * ((size_t)P.nwaves + P.ncells_wide);
     b += 3 * 8 * nt;                           // one MSD origin (more on demand)
     b += 8 * (size_t)n_rep;                    // per-replica kernel arguments
     return b;
@@ -229,6 +264,8 @@ extern "C" int md_workspace_size(const kamd_config *cfg, const kamd_replica *rep
     if (!bytes) return fail(nullptr, KAMD_EINVAL, "bytes is null");
     Plan P;
     make_plan(cfg, reps, n_rep, list_skin(cfg), cfg->cell_div <= 0 ? 1 : cfg->cell_div, P);
+    rc = plan_fits(nullptr, P);
+    if (rc) return rc;
     *bytes = plan_bytes(P, n_rep);
     return KAMD_OK;
 }
@@ -250,6 +287,7 @@ extern "C" int md_admit(const kamd_config *cfg, const kamd_replica *reps, int32_
         size_t b = 0;
         if (v == KAMD_OK) {
             make_plan(cfg, acc.data(), (int)acc.size(), list_skin(cfg), cfg->cell_div <= 0 ? 1 : cfg->cell_div, P);
+            if (P.ncells_wide > MAX_PLAN_CELLS) v = KAMD_EINVAL;
             b = plan_bytes(P, (int)acc.size());
         }
         if (v == KAMD_OK && b <= budget) {
@@ -356,6 +394,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     d.n_total = P.n_total;
     d.nwaves = P.nwaves;
     d.nrep = (int32_t)c->reps.size();
+    d.dim = dim_of(&c->cfg);
     double **f64[] = {&d.x, &d.y, &d.z, &d.vx, &d.vy, &d.vz, &d.ax, &d.ay, &d.az,
                       &d.sx, &d.sy, &d.sz, &d.svx, &d.svy, &d.svz, &d.sax, &d.say, &d.saz};
     for (auto p : f64) TRY(dalloc(c, p, np));
@@ -418,7 +457,8 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
 // Random sequential addition: uniform proposals, accepted when no placed
 // particle is closer than dmin (minimum image); the first n_a accepted are A.
 // Falls back to the lattice when the attempt budget runs out.
-static bool rsa_positions(const kamd_replica &K, double dmin, std::vector<double> &x, std::vector<double> &y,
+// dim 2: the plane z = 0 (planar system), with a square cell grid.
+static bool rsa_positions(const kamd_replica &K, int dim, double dmin, std::vector<double> &x, std::vector<double> &y,
                           std::vector<double> &z)
 {
     const int n = K.n;
@@ -428,7 +468,8 @@ static bool rsa_positions(const kamd_replica &K, double dmin, std::vector<double
     int nc = std::max(1, (int)std::floor(L / dmin));
     if (nc < 3) nc = 1;
     const double cw = L / nc;
-    std::vector<int> head((size_t)nc * nc * nc, -1), next(n, -1);
+    const int ncz = dim == 2 ? 1 : nc;
+    std::vector<int> head((size_t)nc * nc * ncz, -1), next(n, -1);
     x.resize(n);
     y.resize(n);
     z.resize(n);
@@ -439,14 +480,16 @@ static bool rsa_positions(const kamd_replica &K, double dmin, std::vector<double
     auto mi = [L](double d) { if (d > 0.5 * L) d -= L; else if (d < -0.5 * L) d += L; return d; };
     while (placed < n && tries < budget) {
         ++tries;
-        double px = U(rng), py = U(rng), pz = U(rng);
-        int cx = std::min(nc - 1, (int)(px / cw)), cy = std::min(nc - 1, (int)(py / cw)), cz = std::min(nc - 1, (int)(pz / cw));
+        double px = U(rng), py = U(rng), pz = dim == 2 ? 0.0 : U(rng);
+        int cx = std::min(nc - 1, (int)(px / cw)), cy = std::min(nc - 1, (int)(py / cw)),
+            cz = dim == 2 ? 0 : std::min(nc - 1, (int)(pz / cw));
         bool ok = true;
         const int lo = nc >= 3 ? -1 : 0, hi = nc >= 3 ? 1 : 0;
-        for (int oz = lo; oz <= hi && ok; ++oz)
+        const int zlo = dim == 2 ? 0 : lo, zhi = dim == 2 ? 0 : hi;
+        for (int oz = zlo; oz <= zhi && ok; ++oz)
             for (int oy = lo; oy <= hi && ok; ++oy)
                 for (int ox = lo; ox <= hi && ok; ++ox) {
-                    int q = (((cz + oz + nc) % nc) * nc + (cy + oy + nc) % nc) * nc + (cx + ox + nc) % nc;
+                    int q = (((cz + oz + ncz) % ncz) * nc + (cy + oy + nc) % nc) * nc + (cx + ox + nc) % nc;
                     for (int j = head[q]; j >= 0; j = next[j]) {
                         double dx = mi(px - x[j]), dy = mi(py - y[j]), dz = mi(pz - z[j]);
                         if (dx * dx + dy * dy + dz * dz < d2) { ok = false; break; }
@@ -466,12 +509,13 @@ static bool rsa_positions(const kamd_replica &K, double dmin, std::vector<double
 
 // Simple cubic lattice sites (0.5 + k) L/m, then each B particle swaps its
 // site with a randomly chosen A particle (Sec. III.A).
-static void lattice_positions(const kamd_replica &K, std::vector<double> &x, std::vector<double> &y,
+// dim 2: a square lattice in the plane z = 0.
+static void lattice_positions(const kamd_replica &K, int dim, std::vector<double> &x, std::vector<double> &y,
                               std::vector<double> &z)
 {
     const int n = K.n;
-    int m = (int)std::ceil(std::cbrt((double)n) - 1e-9);
-    while ((int64_t)m * m * m < n) ++m;
+    int m = dim == 2 ? (int)std::ceil(std::sqrt((double)n) - 1e-9) : (int)std::ceil(std::cbrt((double)n) - 1e-9);
+    while ((dim == 2 ? (int64_t)m * m : (int64_t)m * m * m) < n) ++m;
     const double a = K.box / m;
     x.resize(n);
     y.resize(n);
@@ -479,7 +523,7 @@ static void lattice_positions(const kamd_replica &K, std::vector<double> &x, std
     for (int i = 0; i < n; ++i) {
         x[i] = (0.5 + i % m) * a;
         y[i] = (0.5 + (i / m) % m) * a;
-        z[i] = (0.5 + i / (m * m)) * a;
+        z[i] = dim == 2 ? 0.0 : (0.5 + i / (m * m)) * a;
     }
     std::mt19937_64 rng(K.seed ^ 0x4c41545449434531ull);
     if (K.n_a > 0)
@@ -617,8 +661,8 @@ static int set_Q(kamd_ctx *c, double tau)
 {
     std::vector<double> Q(c->reps.size());
     for (size_t r = 0; r < Q.size(); ++r) {
-        Q[r] = 3.0 * c->reps[r].n * c->reps[r].temperature * tau * tau;
-        if (!(Q[r] > 0.0)) return fail(c, KAMD_EINVAL, "Nose-Hoover bath mass Q = 3 N T tau^2 must be > 0 (replica %zu)", r);
+        Q[r] = (double)dim_of(&c->cfg) * c->reps[r].n * c->reps[r].temperature * tau * tau;
+        if (!(Q[r] > 0.0)) return fail(c, KAMD_EINVAL, "Nose-Hoover bath mass Q = d N T tau^2 must be > 0 (replica %zu)", r);
     }
     HIPCHK(c, hipMemcpyAsync(c->Q_dev, Q.data(), 8 * Q.size(), hipMemcpyHostToDevice, c->stream));
     return KAMD_OK;
@@ -633,6 +677,7 @@ static int apply_list_params(kamd_ctx *c, double skin, int cell_div, bool first)
     if (cell_div < 1 || cell_div > 2) return fail(c, KAMD_EINVAL, "cell_div must be 1 or 2");
     Plan P;
     make_plan(&c->cfg, c->reps.data(), (int)c->reps.size(), skin, cell_div, P);
+    TRY(plan_fits(c, P));
     c->skin = skin;
     c->cell_div = cell_div;
     c->segs = P.segs;
@@ -708,8 +753,9 @@ extern "C" int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replic
                 const kamd_replica &K = c->reps[q];
                 std::vector<double> x, y, z;
                 bool ok = false;
-                if (cfg->init_mode == KAMD_INIT_RSA) ok = rsa_positions(K, cfg->min_dist > 0 ? cfg->min_dist : 0.8, x, y, z);
-                if (!ok) lattice_positions(K, x, y, z);
+                const int dm = dim_of(cfg);
+                if (cfg->init_mode == KAMD_INIT_RSA) ok = rsa_positions(K, dm, cfg->min_dist > 0 ? cfg->min_dist : 0.8, x, y, z);
+                if (!ok) lattice_positions(K, dm, x, y, z);
                 std::copy(x.begin(), x.end(), hx.begin() + K.offset);
                 std::copy(y.begin(), y.end(), hy.begin() + K.offset);
                 std::copy(z.begin(), z.end(), hz.begin() + K.offset);
@@ -834,13 +880,17 @@ extern "C" int md_rdf(kamd_ctx *c, double dr, int32_t n_bins, uint64_t *hist_dev
     for (size_t r = 0; r < c->reps.size(); ++r) {
         const double L = c->reps[r].box;
         if (rmax > 0.5 * L * (1.0 + 1e-12)) return fail(c, KAMD_EINVAL, "n_bins*dr = %.9g exceeds L/2 = %.9g (replica %zu)", rmax, 0.5 * L, r);
-        int nc = std::max(1, (int)std::floor(L / rmax));
-        nc = std::min(nc, 512);
+        const bool planar = dim_of(&c->cfg) == 2;
+        const int nc = (int)std::max(1.0, std::min(std::floor(L / rmax), (double)cell_cap(dim_of(&c->cfg))));
+        const int ncell = planar ? nc * nc : nc * nc * nc;
         c->rinfo[r].rdf_nc = nc;
-        c->rinfo[r].rdf_cell0 = (int32_t)cells;
-        c->rinfo[r].rdf_ncell = nc * nc * nc;
-        cells += (int64_t)nc * nc * nc;
+        c->rinfo[r].rdf_cell0 = (int32_t)std::min<int64_t>(cells, INT32_MAX);
+        c->rinfo[r].rdf_ncell = ncell;
+        cells += ncell;
     }
+    if (cells > MAX_PLAN_CELLS)
+        return fail(c, KAMD_EINVAL, "RDF cell grid of %lld cells exceeds the limit of %lld (larger n_bins*dr)",
+                    (long long)cells, (long long)MAX_PLAN_CELLS);
     Dev &d = c->d;
     if (cells > c->rdf_cells_cap) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -910,14 +960,15 @@ extern "C" int md_observables(kamd_ctx *c, double *host_out)
     for (size_t r = 0; r < nr; ++r) {
         const double KE = 0.5 * ke[4 * r + 0];
         const double PE = pw[4 * r + 1], W = pw[4 * r + 2];
-        const double n = c->reps[r].n, L = c->reps[r].box, V = L * L * L;
-        const double T = 2.0 * KE / (3.0 * n);
+        const double dd = (double)dim_of(&c->cfg);
+        const double n = c->reps[r].n, L = c->reps[r].box, V = dd == 2.0 ? L * L : L * L * L;
+        const double T = 2.0 * KE / (dd * n);
         host_out[6 * r + 0] = KE;
         host_out[6 * r + 1] = PE;
         host_out[6 * r + 2] = W;
         host_out[6 * r + 3] = T;
         host_out[6 * r + 4] = KE + PE;
-        host_out[6 * r + 5] = n * T / V + W / (3.0 * V);
+        host_out[6 * r + 5] = n * T / V + W / (dd * V);
     }
     return KAMD_OK;
 }

@@ -103,6 +103,28 @@ def ka_small() -> Workload:
     return single("ka_n1000_rho1.2_T2.0_nve", 1000, 1.2, 2.0, 1, 1000)
 
 
+def ka_planar(n: int = 1000, T: float = 0.4) -> Workload:
+    """The planar KA variant of the appendix exercise: 65:35 mixture at
+    N/L^2 = 1.204 (L = 28.82 for N = 1000), z = vz = 0, T < 0.5."""
+    L = float(np.sqrt(n / 1.204))
+    rep = Replica(n=n, n_a=n_a_for(n, 0.65), box=L, temperature=T, seed=BASE_SEED + 7000, rho=1.204)
+    return Workload(name=f"ka2d_n{n}_rho1.204_T{T}", replicas=[rep], steps=1000)
+
+
+def planar_lattice_config(n: int, L: float, seed: int, jitter: float = 0.05):
+    """Positions on a square lattice in the plane z = 0 with uniform jitter,
+    random site order (x, y, z with z = 0)."""
+    m = int(np.ceil(np.sqrt(n) - 1e-9))
+    while m * m < n:
+        m += 1
+    a = L / m
+    rng = np.random.default_rng(seed)
+    sites = rng.permutation(m * m)[:n]
+    x = (sites % m + 0.5 + rng.uniform(-jitter, jitter, n)) * a
+    y = (sites // m + 0.5 + rng.uniform(-jitter, jitter, n)) * a
+    return np.mod(x, L), np.mod(y, L), np.zeros(n)
+
+
 def ka_medium() -> Workload:
     """N = 32,000 (25,600 A / 6,400 B) at density 1.2, T = 0.5."""
     return single("ka_n32000_rho1.2_T0.5", 32000, 1.2, 0.5, 2, 10000)

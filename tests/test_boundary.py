@@ -64,6 +64,35 @@ def test_validation_errors():
         md.md_workspace_size(bad, _reps([500]))
 
 
+def test_planar_cell_grid_is_one_layer():
+    """A planar system bins into nc^2 cells: at 2^20 particles (L = 933) the
+    footprint stays near the list size and hardly depends on the cell
+    division (a cubic grid would need 2 * 333^3 cells at division 1 and
+    2 * 666^3 at division 2, i.e. over a gigabyte of cell tables)."""
+    wl = W.ka_planar(1 << 20, 0.4)
+    r = wl.replicas[0]
+    reps = md.make_replicas([(r.n, r.n_a, r.box, r.temperature, r.seed)])
+    one = md.md_workspace_size(md.make_config(precision="mixed_fixed", dim=2, cell_div=1), reps)
+    two = md.md_workspace_size(md.make_config(precision="mixed_fixed", dim=2, cell_div=2), reps)
+    assert one < 1 << 30 and two < 1 << 30
+    # division 1: 2 * 333^2 cells; division 2: 2 * 666^2; 16 bytes per cell
+    assert abs(two - one) < 16 * 2 * 700 ** 2
+
+
+def test_cell_grid_limits():
+    """Cells per edge are capped (wider cells stay correct), and a plan whose
+    cell grid would exceed 2^28 cells in all is refused, not truncated."""
+    cfg = md.make_config()
+    sparse = [(1000, 800, 800.0, 1.0, 3 + i) for i in range(9)]  # 2 * 256^3 cells each after the cap
+    eight = md.md_workspace_size(cfg, md.make_replicas(sparse[:8]))
+    assert eight < 16 * (1 << 28) + (1 << 28)
+    with pytest.raises(md.KamdError) as e:
+        md.md_workspace_size(cfg, md.make_replicas(sparse))
+    assert e.value.code == md.KAMD_EINVAL and "cell grid" in str(e.value)
+    adm, cnt = md.md_admit(cfg, md.make_replicas(sparse), 10 ** 12)
+    assert cnt == 8 and adm.tolist() == [1] * 8 + [0]
+
+
 def test_admission_by_footprint():
     cfg = md.make_config()
     reps = _reps([2000, 4000, 8000, 3000])

@@ -53,6 +53,57 @@ def test_large_system_forces_match_oracle(prec, tol):
     s.close()
 
 
+def test_large_system_forces_cell_division_2():
+    """Half-width cells at 2^20 particles: 2 * 64^3 = 524,288 cells, more than
+    one pass of the capped per-cell sort grid, so its stride loop is used."""
+    r, pos, vel = _large_inputs()
+    log(f"case large forces cell_div 2 n={r.n}")
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision="mixed_fixed", positions=pos,
+                  velocities=vel, skin=0.4, cell_div=2)
+    a = s.numpy(("ax", "ay", "az"))
+    fx, fy, fz, _, _ = O.forces(*pos, r.n_a, r.box, "cell")
+    err = normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz))
+    log(f"  normwise {err:.3e}")
+    assert err <= 1e-5
+    assert s.status() == 0
+    s.close()
+
+
+def test_large_planar_bath_and_autotune_match_oracle():
+    """The planar workload at 2^20 particles (L = 933): the list bins into one
+    layer of nc^2 cells per segment.  After bath steps (with rebuilds) and an
+    autotune over skins and both cell divisions, the forces match the oracle
+    on the resulting positions and every particle stays in the plane."""
+    wl = W.ka_planar(1 << 20, 0.4)
+    r = wl.replicas[0]
+    x, y, z = W.planar_lattice_config(r.n, r.box, r.seed)
+    log(f"case large planar n={r.n} L={r.box:.2f}")
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision="mixed_fixed", dt=wl.dt, skin=0.3,
+                  positions=(x, y, z), auto_sync=False, dim=2)
+    s.step_nvt(300, md.NVT_STOCHASTIC, n_reassign=10)
+    assert s.status() == 0
+    log("  bath done")
+
+    def check():
+        s.sync()
+        a = s.numpy()
+        assert np.all(a["z"] == 0.0) and np.all(a["vz"] == 0.0) and np.all(a["az"] == 0.0)
+        fx, fy, fz, _, _ = O.forces(a["x"], a["y"], a["z"], r.n_a, r.box, "cell")
+        err = normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz))
+        log(f"  normwise {err:.3e}")
+        assert err <= 1e-5
+
+    check()
+    tune = md.md_autotune(s.ctx, 20)
+    log(f"  autotune {tune}")
+    s.step_nvt(100, md.NVT_STOCHASTIC, n_reassign=10)
+    assert s.status() == 0
+    check()
+    st = md.md_stats(s.ctx)
+    assert st["rebuilds"] >= 1 and st["max_list_len"] <= st["list_rows"]
+    s.close()
+
+
 def test_large_system_graph_steps_are_sound():
     """The bench's timed configuration: graph-captured NVE steps at 2^20 particles
     with fixed-point forces; forces after the steps match the oracle on the

@@ -492,3 +492,95 @@ def test_quench_aging_two_time_msd():
     assert np.all(vh[:, :, 0, :].sum(axis=-1) == W.n_a_for(1000))
     assert s.status() == 0
     s.close()
+
+
+_PLANAR = {}
+
+
+def planar_relaxed(n=1000, T=0.4, seed=3):
+    """Oracle-relaxed planar 65:35 liquid at N/L^2 = 1.204 (z = vz = 0)."""
+    key = (n, T, seed)
+    if key not in _PLANAR:
+        wl = W.ka_planar(n, T)
+        r = wl.replicas[0]
+        x, y, z = W.planar_lattice_config(n, r.box, seed)
+        vx, vy, vz = O.mb_velocities(n, T, seed, dim=2)
+        st = O.State(x, y, z, vx, vy, vz, r.n_a, r.box)
+        st.compute_forces()
+        O.run(st, 0.00025, 300, nb=5, T=T, seed=seed, dim=2)
+        O.run(st, 0.002, 1500, nb=10, T=T, seed=seed, dim=2, step0=300)
+        _PLANAR[key] = (st.x.copy(), st.y.copy(), st.z.copy(), st.vx.copy(), st.vy.copy(), st.vz.copy(),
+                        r.n_a, r.box)
+    return _PLANAR[key]
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed_fixed", 1e-5)])
+def test_planar_forces_match_oracle(prec, tol):
+    n = 1000
+    x, y, z, vx, vy, vz, na, L = planar_relaxed(n)
+    log(f"case planar forces {prec}")
+    s = md.System([(n, na, L, 0.4, 5)], precision=prec, positions=(x, y, z), velocities=(vx, vy, vz), dim=2)
+    a = s.numpy(("ax", "ay", "az"))
+    fx, fy, fz, pe, _ = O.forces(x, y, z, na, L, "brute")
+    assert np.all(a["az"] == 0.0) and np.all(fz == 0.0)
+    assert normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz)) <= tol
+    assert s.forces(energy=True)[0, 0] == pytest.approx(pe, rel=max(tol, 1e-12))
+    s.close()
+
+
+def test_planar_bath_nve_and_nose_hoover_match_oracle():
+    """Planar system: the bath redraw is the oracle's planar flow chart
+    (vz = 0, sum v^2 = 2 N T), NVE steps follow the oracle's trajectory and
+    stay in the plane, Nose-Hoover uses X = 2N."""
+    n, T = 1000, 0.4
+    x, y, z, vx, vy, vz, na, L = planar_relaxed(n, T)
+    log("case planar dynamics")
+    s = md.System([(n, na, L, T, 77)], precision="fp64", positions=(x, y, z), velocities=(vx, vy, vz), dim=2)
+    s.step_nvt(10, md.NVT_STOCHASTIC, n_reassign=10)
+    a = s.numpy()
+    rx, ry, rz = O.mb_velocities(n, T, 77, rep=0, tag=10, dim=2)
+    assert np.all(a["vz"] == 0.0) and np.all(a["z"] == 0.0)
+    assert np.max(np.abs(a["vx"] - rx)) < 1e-12 and np.max(np.abs(a["vy"] - ry)) < 1e-12
+    assert s.observables()[0, 3] == pytest.approx(T, rel=1e-12)  # T = 2 KE / (2 N)
+    s.close()
+    s = md.System([(n, na, L, T, 77)], precision="fp64", positions=(x, y, z), velocities=(vx, vy, vz), dim=2,
+                  dt=0.002)
+    st = O.State(x, y, z, vx, vy, vz, na, L)
+    st.compute_forces()
+    O.run(st, 0.002, 40)
+    s.step_nve(40)
+    a = s.numpy()
+    img = s.images()
+    assert np.all(a["z"] == 0.0) and np.all(img[2] == 0)
+    assert np.max(np.abs(a["x"] + img[0] * L - (st.x + st.img[0] * L))) < 1e-9
+    assert np.max(np.abs(a["vy"] - st.vy)) < 1e-9
+    s.close()
+    s = md.System([(n, na, L, T, 77)], precision="fp64", positions=(x, y, z), velocities=(vx, vy, vz), dim=2,
+                  dt=0.002)
+    st = O.State(x, y, z, vx, vy, vz, na, L)
+    st.compute_forces()
+    tau = 0.3
+    O.run_nh(st, 0.002, 20, 0.3, 2 * n * 0.3 * tau ** 2, dim=2)
+    s.set_temperature(0.3)
+    s.step_nvt(20, md.NVT_NOSE_HOOVER, tau=tau)
+    th = md.md_thermostat_state(s.ctx, 1)[0]
+    assert th[0] == pytest.approx(st.xi, rel=1e-9, abs=1e-12)
+    s.close()
+
+
+def test_planar_rsa_init_and_rdf():
+    wl = W.ka_planar()
+    r = wl.replicas[0]
+    log("case planar rsa + rdf")
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision="mixed", init="rsa", dim=2)
+    a = s.numpy()
+    assert np.all(a["z"] == 0.0) and np.all(a["vz"] == 0.0)
+    assert O.min_distance(a["x"], a["y"], a["z"], r.box) >= 0.8 - 1e-12
+    assert s.observables()[0, 3] == pytest.approx(r.temperature, rel=1e-12)
+    dr = 0.05
+    nb = int(r.box / 2 / dr)
+    h = s._host(s.rdf(dr, nb)).astype(np.uint64)[0]
+    assert np.array_equal(h, O.rdf_hist(a["x"], a["y"], a["z"], r.n_a, r.box, dr, nb))
+    s.step_nve(200)
+    assert s.status() == 0 and np.all(s.numpy(("z",))["z"] == 0.0)
+    s.close()
