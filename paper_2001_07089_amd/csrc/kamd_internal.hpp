@@ -109,7 +109,8 @@ struct Dev {
     // cells and lists
     int32_t *cell_of, *rank, *cell_count, *cell_start, *cell_end, *order;
     int32_t *rb_force;    // per replica: rebuild at the next check regardless
-    int32_t *rb_any;      // [1]: some replica rebuilds this step (set by the chain's gate kernel)
+    int32_t *rb_any;      // [1]: number of waves that rebuild this step (set by the chain's gate kernel)
+    int32_t *rb_wlist;    // [nwaves]: those waves, replica by replica (set by the gate kernel)
     uint32_t *maxdisp;    // per replica: max |r - r_build|^2 (float bits) since the last check
     int32_t *nbr;         // per wave: rows x 64 entries, see list_index
     int2 *kmax;           // per wave: rows of the A part, rows of the B part

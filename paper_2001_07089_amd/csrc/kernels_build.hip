@@ -11,42 +11,107 @@
 // rebuilt when some particle of the replica has moved more than skin/2 since
 // the last build (so no pair can enter the cutoff unseen).
 //
-// A rebuild runs as five kernels.  Each one evaluates the replica's rebuild
-// flag itself (rebuild_flag) and returns at once when it is clear, so the
-// decision stays on the device and the step loop can be captured in a HIP
-// graph:
-//   rb_assign     per particle: cell index, rank inside the cell (one atomic
-//                 per run of lanes that share a cell)
+// A rebuild runs as a gate and five kernels, all launched on every step, so
+// that the decision stays on the device and the step loop can be captured in
+// a HIP graph:
+//   rb_gate       one block: rebuild flag of every replica (rebuild_flag),
+//                 worklist of the waves of the replicas that rebuild
+//   rb_assign     per listed wave: cell index and rank inside the cell of its
+//                 particles (one atomic per run of lanes that share a cell)
 //   rb_scan       per segment: exclusive scan of the counters -> cell ranges
-//   rb_scatter    per particle: provisional destination slot
+//   rb_scatter    per listed wave: provisional destination slot
 //   rb_sortgather per cell: order the cell by previous slot (a stable sort:
 //                 the result does not depend on atomic timing), gather the
 //                 particles' state into the scratch arrays, clear the counter
-//   rb_list       per particle: copy its state back, record the build
+//   rb_list       per listed wave: copy its state back, record the build
 //                 position, write its neighbour list
+// Every kernel returns at once when the worklist is empty; the per-segment
+// and per-cell kernels also skip replicas whose flag is clear.
 #include <climits>
 
 #include "common_dev.hpp"
 
 namespace kamd {
 
-// The gate: one block ORs the rebuild flags of all replicas into rb_any, so
-// that on the (most frequent) steps without a rebuild every later kernel of
-// the chain exits after one load.
-__global__ __launch_bounds__(BLOCK) void k_rb_gate(Dev d)
+// The gate: one block evaluates the rebuild flag of every replica and writes
+// the waves of the replicas that rebuild into the worklist rb_wlist (replica
+// by replica, in slot order), with their count in rb_any.  On the (most
+// frequent) steps without a rebuild every later kernel of the chain exits
+// after one load; on a step where a few replicas of a batch rebuild, the
+// per-wave kernels spread just those waves over the whole device.
+constexpr int GATE_THREADS = 1024;
+
+__global__ __launch_bounds__(GATE_THREADS) void k_rb_gate(Dev d)
 {
-    int any = 0;
-    for (int r = threadIdx.x; r < d.nrep; r += BLOCK) any |= rebuild_flag(d, r) ? 1 : 0;
-    any = __syncthreads_or(any);
-    if (threadIdx.x == 0) d.rb_any[0] = any;
+    __shared__ int pre[GATE_THREADS + 1];  // exclusive prefix of the wave counts of one chunk of replicas
+    __shared__ int first[GATE_THREADS];    // first wave of each replica of the chunk
+    __shared__ int wtot[GATE_THREADS / WAVE];
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+    int base = 0;
+    for (int r0 = 0; r0 < d.nrep; r0 += GATE_THREADS) {
+        const int r = r0 + t;
+        int nw = 0;
+        first[t] = 0;
+        if (r < d.nrep) {
+            first[t] = d.rep[r].wave0;
+            if (rebuild_flag(d, r)) nw = d.rep[r].wave1 - d.rep[r].wave0;
+        }
+        int inc = nw;  // inclusive scan over the wavefront, then over the wavefront totals
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const int u = __shfl_up(inc, o, WAVE);
+            if (lane >= o) inc += u;
+        }
+        if (lane == WAVE - 1) wtot[wv] = inc;
+        __syncthreads();
+        if (t == 0) {
+            int run = 0;
+            for (int k = 0; k < GATE_THREADS / WAVE; ++k) {
+                const int x = wtot[k];
+                wtot[k] = run;
+                run += x;
+            }
+            pre[GATE_THREADS] = run;
+        }
+        __syncthreads();
+        pre[t] = wtot[wv] + inc - nw;
+        __syncthreads();
+        const int tot = pre[GATE_THREADS];
+        // entry i belongs to the last replica k of the chunk with pre[k] <= i,
+        // which is one that rebuilds (a replica without waves shares its
+        // prefix with the next one)
+        for (int i = t; i < tot; i += GATE_THREADS) {
+            int lo = 0, hi = GATE_THREADS - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= i) lo = mid;
+                else hi = mid - 1;
+            }
+            d.rb_wlist[base + i] = first[lo] + (i - pre[lo]);
+        }
+        base += tot;
+        __syncthreads();  // the chunk's shared arrays are reused
+    }
+    if (t == 0) d.rb_any[0] = base;
 }
 
-// The per-particle kernels of the chain walk their work units
-// with a grid stride over a capped grid (their work per unit is small).
+// Worklist entry of this wavefront for the per-wave kernels that run one
+// wave per worklist entry: the first ceil(count / WAVES_PER_BLOCK) blocks
+// take part, each XCD a contiguous part of the list; -1 for the rest.
+__device__ inline int rb_work_wave(const Dev &d)
+{
+    const int nact = d.rb_any[0];
+    const int nab = (nact + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    if ((int)blockIdx.x >= nab) return -1;
+    const int i = xcd_block(blockIdx.x, nab) * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    return i < nact ? d.rb_wlist[i] : -1;
+}
+
+// The per-particle kernels of the chain walk the worklist with a grid
+// stride over a capped grid (their work per unit is small).
 __device__ inline void assign_wave(const Dev &d, int w)
 {
     const SegInfo &S = d.seg[d.wave_seg[w]];
-    if (!rebuild_flag(d, S.rep)) return;
     const int lane = lane_id();
     const int s = w * WAVE + lane;
     const bool real = (s - S.slot0) < S.n;
@@ -76,9 +141,11 @@ __device__ inline void assign_wave(const Dev &d, int w)
 
 __global__ __launch_bounds__(BLOCK) void k_rb_assign(Dev d)
 {
-    if (d.rb_any[0] == 0) return;
+    const int nact = d.rb_any[0];
+    if (nact == 0) return;
     const int stride = gridDim.x * WAVES_PER_BLOCK;
-    for (int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); w < d.nwaves; w += stride) assign_wave(d, w);
+    for (int i = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); i < nact; i += stride)
+        assign_wave(d, d.rb_wlist[i]);
 }
 
 // Exclusive scan of one segment's cell counters into absolute slot ranges
@@ -139,11 +206,12 @@ __global__ __launch_bounds__(1024) void k_rb_scan(Dev d)
 
 __global__ __launch_bounds__(BLOCK) void k_rb_scatter(Dev d)
 {
-    if (d.rb_any[0] == 0) return;
+    const int nact = d.rb_any[0];
+    if (nact == 0) return;
     const int stride = gridDim.x * WAVES_PER_BLOCK;
-    for (int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); w < d.nwaves; w += stride) {
+    for (int i = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); i < nact; i += stride) {
+        const int w = d.rb_wlist[i];
         const SegInfo &S = d.seg[d.wave_seg[w]];
-        if (!rebuild_flag(d, S.rep)) continue;
         const int s = w * WAVE + lane_id();
         if (s - S.slot0 < S.n) d.order[d.cell_start[d.cell_of[s]] + d.rank[s]] = s;
     }
@@ -254,11 +322,10 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     __shared__ int32_t stage[WAVES_PER_BLOCK][LIST_STAGE][WAVE];
     __shared__ uint32_t win_s[WAVES_PER_BLOCK][3][LIST_WIN + LIST_UNROLL];
     if (d.rb_any[0] == 0) return;
-    const int w = wave_id_remapped();  // each XCD walks a contiguous slot range
-    if (w >= d.nwaves) return;
+    const int w = rb_work_wave(d);  // each XCD walks a contiguous part of the worklist
+    if (w < 0) return;
     const SegInfo &S = d.seg[d.wave_seg[w]];
     const int rep = S.rep;
-    if (!rebuild_flag(d, rep)) return;
     const RepInfo &R = d.rep[rep];
     const int lane = lane_id();
     const int s = w * WAVE + lane;
@@ -468,7 +535,7 @@ static inline int nblk_capped(int waves) { return std::min((waves + WAVES_PER_BL
 
 hipError_t launch_rb_gate(const Dev &d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rb_gate, dim3(1), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_rb_gate, dim3(1), dim3(GATE_THREADS), 0, s, d);
     return hipGetLastError();
 }
 hipError_t launch_rb_assign(const Dev &d, hipStream_t s)

@@ -254,6 +254,7 @@ static size_t plan_bytes(const Plan &P, int n_rep)
     b += (sizeof(SegInfo) + sizeof(RepInfo)) * 2 * (size_t)n_rep + 4 * ((size_t)P.nwaves + P.ncells_wide);
     b += 3 * 8 * nt;                           // one MSD origin (more on demand)
     b += 8 * (size_t)n_rep;                    // per-replica kernel arguments
+    b += 4 * (size_t)P.nwaves;                 // rebuild worklist
     return b;
 }
 
@@ -420,6 +421,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     TRY(dalloc(c, &d.nlen, np));
     TRY(dalloc(c, &d.rb_force, d.nrep));
     TRY(dalloc(c, &d.rb_any, 1));
+    TRY(dalloc(c, &d.rb_wlist, P.nwaves));
     TRY(dalloc(c, &c->md_base, 2 * (size_t)d.nrep));
     d.maxdisp = c->md_base;
     TRY(dalloc(c, &c->mirror_alt, np));
