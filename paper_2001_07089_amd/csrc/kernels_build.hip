@@ -272,8 +272,9 @@ __global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
 
 // Neighbour lists.  One thread per particle.  Entries [0, kA) of a list hold
 // the particle's A partners, entries [kA, kA + kB) its B partners, where kA,
-// kB are the wavefront maxima rounded up to LIST_ROW_ALIGN; unused entries
-// hold the particle's own slot, which the force kernels skip (zero
+// kB are the wavefront maxima rounded up to LIST_ROW_ALIGN.  The part of the
+// particle's own type also holds its own slot once (it passes the distance
+// test), and unused entries hold it too; the force kernels skip it (zero
 // separation).  Storage follows list_index: a particle appends 16 contiguous
 // bytes at a time, so cache lines fill completely before they leave the L2.
 //
@@ -389,25 +390,38 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         // not it is accepted; only an accepted one advances the count.  At
         // the start of a batch at most LIST_STAGE - LIST_UNROLL entries are
         // pending, so the slot written is never one still to be flushed.
-        auto test = [&](int j, int en, uint32_t jx, uint32_t jy, uint32_t jz) {
+        // The particle's own slot passes the test (zero separation) and stays
+        // in its list, where the force kernels skip it like the padding.
+        // `in` is false only past the end of a range, in the last batch.
+        auto test = [&](int j, bool in, uint32_t jx, uint32_t jy, uint32_t jz) {
             const float dx = (float)(int)(mi.x - jx);
             const float dy = (float)(int)(mi.y - jy);
             const float dz = (float)(int)(mi.z - jz);
             const float r2 = dx * dx + dy * dy + dz * dz;
-            const int acc = (int)(j < en) & (int)(r2 < rl2) & (int)(r2 > 0.0f);
+            const int acc = (int)in & (int)(r2 < rl2);
             buf[cnt & (LIST_STAGE - 1)][lane] = j;
             cnt += acc;
         };
         auto scan = [&](int st, int en) {  // straight from global memory
-            for (int j = st; j < en; j += LIST_UNROLL) {
+            int j = st;
+            for (; j + LIST_UNROLL <= en; j += LIST_UNROLL) {  // whole batches
                 const uint4 *src = d.smirror + j;
                 uint4 mj[LIST_UNROLL];
 #pragma unroll
                 for (int u = 0; u < LIST_UNROLL; ++u) mj[u] = src[u];
 #pragma unroll
-                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, en, mj[u].x, mj[u].y, mj[u].z);
+                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, true, mj[u].x, mj[u].y, mj[u].z);
                 if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
             }
+            if (j < en) {  // the last, partial batch
+                const uint4 *src = d.smirror + j;
+                uint4 mj[LIST_UNROLL];
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) mj[u] = src[u];
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, j + u < en, mj[u].x, mj[u].y, mj[u].z);
+            }
+            if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
         };
         auto scan_staged = [&](int st, int en) {  // all lanes of the wavefront take part
             const bool has = st < en;
@@ -426,12 +440,19 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            for (int j = st; j < en; j += LIST_UNROLL) {
+            int j = st;
+            for (; j + LIST_UNROLL <= en; j += LIST_UNROLL) {  // whole batches
                 const int o = j - lo;
 #pragma unroll
-                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, en, wx[o + u], wy[o + u], wz[o + u]);
+                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, true, wx[o + u], wy[o + u], wz[o + u]);
                 if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
             }
+            if (j < en) {  // the last, partial batch
+                const int o = j - lo;
+#pragma unroll
+                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, j + u < en, wx[o + u], wy[o + u], wz[o + u]);
+            }
+            if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         };
@@ -525,7 +546,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         kpart[1] = min(kpart[1], rows - kpart[0]);
     }
     if (lane == 0) d.kmax[w] = make_int2(kpart[0], kpart[1]);
-    d.nlen[s] = total;
+    d.nlen[s] = real ? total - 1 : 0;  // partners, without the own slot
 }
 
 static inline int nblk_slots(const Dev &d) { return (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
