@@ -167,6 +167,15 @@ def time_analysis(s, md, rep):
     s.stream.synchronize()
     t_rdf = time.perf_counter() - t0
     counts = s._host(h).astype(np.int64)[0].sum(axis=1)
+    # the LAMMPS compute rdf layout: 25 bins to the force cutoff 2.5, with
+    # coordination numbers (host normalisation of the device counts)
+    from paper_2001_07089_amd import analysis
+    s.rdf(2.5 / 25, 25)
+    s.stream.synchronize()
+    t0 = time.perf_counter()
+    h25 = s.rdf(2.5 / 25, 25)
+    table = analysis.lammps_rdf(s._host(h25)[0], rep.n, rep.n_a, rep.box, 2.5)
+    t_lmp = time.perf_counter() - t0
     s.msd_set_origin(1)
     s.step_nve(100)
     s.stream.synchronize()
@@ -176,6 +185,8 @@ def time_analysis(s, md, rep):
     torch.cuda.synchronize()
     return {"rdf_ms": t_rdf * 1e3, "rdf_r_max": 5.0, "rdf_bins": 200,
             "rdf_pair_counts_AA_AB_BB": [int(c) for c in counts],
+            "lammps_rdf_ms": t_lmp * 1e3, "lammps_rdf_coordination_at_2.5_AA_BB_AB":
+                [float(table[-1, 3]), float(table[-1, 5]), float(table[-1, 7])],
             "msd_ms": t_msd * 1e3, "msd_after_100_steps_A_B": [float(m[0, 0]), float(m[0, 1])]}
 
 

@@ -129,6 +129,12 @@ typedef struct {
                                box is L x L at number density N/L^2, the bath and
                                temperature use 2N degrees of freedom, pressure
                                uses the area                                      */
+    int32_t pe_unshifted;   /* 0: potential energy of the truncated and shifted
+                               potential, Eq. (VshiftedKALJ) (the paper's Python
+                               programs); 1: without the shift V_ab(r_c), the
+                               energy LAMMPS pair style lj/cut reports (Sec. IV.B).
+                               Forces are the same either way; only PE, E_tot and
+                               everything derived from them change               */
 } kamd_config;
 
 /* Device bytes md_init would allocate for this configuration (host call, no

@@ -266,6 +266,69 @@ def rdf_normalize(hist, n, na, L, dr, nmeas, dim: int = 3):
     return rmid, g
 
 
+def pe_lj_cut(x, y, z, na, L, m: Model = None):
+    """Potential energy of the truncated pair potential without the shift:
+    the sum over pairs closer than r_c(ab) of Eq. (VKALJ) alone, i.e. the
+    constant V_ab(r_c) of Eq. (VshiftedKALJ) left out.  This is the energy
+    LAMMPS pair style lj/cut reports (Sec. IV.B notes that it omits that term);
+    the forces are the same.  Plain brute force over all pairs, minimum image
+    by rounding (Sec. II.C), FP64."""
+    m = m or model()
+    x, y, z = (np.asarray(a, np.float64) for a in (x, y, z))
+    n = x.size
+    typ = (np.arange(n) >= na).astype(np.int64)
+    eps = np.array(m.eps[:], np.float64)
+    sig = np.array(m.sigma[:], np.float64)
+    e = 0.0
+    for i in range(n - 1):
+        dx = x[i + 1:] - x[i]
+        dy = y[i + 1:] - y[i]
+        dz = z[i + 1:] - z[i]
+        dx -= L * np.round(dx / L)
+        dy -= L * np.round(dy / L)
+        dz -= L * np.round(dz / L)
+        r2 = dx * dx + dy * dy + dz * dz
+        p = typ[i] + typ[i + 1:]
+        rc = m.rc_factor * sig[p]
+        sel = r2 < rc * rc
+        sr6 = (sig[p][sel] ** 2 / r2[sel]) ** 3
+        e += float(np.sum(4.0 * eps[p][sel] * (sr6 * sr6 - sr6)))
+    return e
+
+
+def lammps_rdf_table(hist, n, na, L, rcut, nbins, nmeas=1):
+    """The table of LAMMPS compute rdf (Sec. VI.A.3): nbins bins of width
+    rcut / nbins from 0, and per pair type I-J (order AA, BB, AB as in the
+    paper's command) g_IJ and the coordination number c_IJ, the mean number of
+    J particles within the bin's outer radius of an I particle.
+
+    hist: [3][nbins] pair-distance counts over nmeas measurements with rows AA
+    (2 per pair), AB (1 per pair), BB (2 per pair), i.e. ordered I-J pairs.
+    g_IJ(bin) = counts / (nmeas N_I (N_J - [I = J]) v_bin / V), with v_bin the
+    shell volume; c_IJ(bin) = sum over bins <= bin of counts / (nmeas N_I).
+    Returns rows [bin number (1-based), r at the bin centre, g_AA, c_AA, g_BB,
+    c_BB, g_AB, c_AB]."""
+    nb = n - na
+    dr = rcut / nbins
+    V = L ** 3
+    rows = []
+    # (hist row, N_I, N_J, same type)
+    pairs = ((0, na, na, True), (2, nb, nb, True), (1, na, nb, False))
+    cum = [0.0, 0.0, 0.0]
+    for b in range(nbins):
+        rin, rout = b * dr, (b + 1) * dr
+        shell = (4.0 * math.pi / 3.0) * (rout ** 3 - rin ** 3)
+        row = [b + 1, rin + 0.5 * dr]
+        for k, (h, ni, nj, same) in enumerate(pairs):
+            cnt = float(hist[h][b]) / nmeas
+            njj = nj - 1 if same else nj
+            g = cnt / (ni * njj * shell / V) if ni > 0 and njj > 0 else 0.0
+            cum[k] += cnt / ni if ni > 0 else 0.0
+            row += [g, cum[k]]
+        rows.append(row)
+    return np.array(rows, np.float64)
+
+
 def msd(x, y, z, img, na, L, x0u, y0u, z0u):
     """Per-species MSD of unwrapped positions against an unwrapped origin."""
     out = np.zeros(2)

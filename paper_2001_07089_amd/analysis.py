@@ -1,5 +1,12 @@
 """Normalisation of the on-device histograms (host side).
 
+lammps_rdf: the table of LAMMPS compute rdf (Sec. VI.A.3) from the same
+counts, taken with n_bins = N_bin and dr = r_cut / N_bin: per pair type g and
+the coordination number (mean number of partners of the second type within
+the bin's outer radius), columns in the order the paper's command requests
+them (AA, BB, AB); write_lammps_rdf writes it in the layout of fix ave/time
+mode vector.
+
 rdf: g_ab(r) from the pair-distance counts of ``md_rdf`` (Eqs. (gAA),
 (gAB) and the normalisation described in Sec. VI.A.1): the counts of bin b
 (AA and BB rows hold 2 per pair, AB 1) divided by the number of measurements,
@@ -50,3 +57,40 @@ def van_hove_self(hist, n: int, n_a: int, dr: float, dim: int = 3):
     ok = counts > 0
     G[ok] = h[ok] / (counts[ok, None] * size[None, :])
     return r, G
+
+
+def lammps_rdf(hist, n: int, n_a: int, L: float, r_cut: float, n_meas: int = 1, dim: int = 3):
+    """hist: [3][N_bin] counts of one replica (rows AA, AB, BB as md_rdf
+    returns them: ordered pairs, so 2 per AA or BB pair and 1 per AB pair),
+    accumulated over n_meas measurements with dr = r_cut / N_bin.  Returns an
+    [N_bin][8] array: bin number (from 1), r at the bin centre, g_AA, c_AA,
+    g_BB, c_BB, g_AB, c_AB.  g_IJ = counts V / (N_I (N_J - [I = J]) v_bin);
+    c_IJ = running sum of counts / N_I."""
+    h = np.asarray(hist, np.float64) / float(n_meas)
+    nbins = h.shape[1]
+    r, size = shells(nbins, r_cut / nbins, dim)
+    V = float(L) ** dim
+    n_b = n - n_a
+    out = np.zeros((nbins, 8))
+    out[:, 0] = np.arange(1, nbins + 1)
+    out[:, 1] = r
+    for col, row, ni, nj in ((2, 0, n_a, n_a - 1), (4, 2, n_b, n_b - 1), (6, 1, n_a, n_b)):
+        if ni > 0 and nj > 0:
+            out[:, col] = h[row] * V / (ni * nj * size)
+        if ni > 0:
+            out[:, col + 1] = np.cumsum(h[row]) / ni
+    return out
+
+
+def write_lammps_rdf(f, blocks, fix_id: str = "myrdf", compute_id: str = "rdfAABBAB"):
+    """Write (step, table) blocks in the layout of fix ave/time mode vector
+    over the compute rdf array: three comment lines, then per block a line
+    'step rows' and one line per bin with the row number and the columns."""
+    f.write(f"# Time-averaged data for fix {fix_id}\n")
+    f.write("# TimeStep Number-of-rows\n")
+    f.write("# Row " + " ".join(f"c_{compute_id}[{k}]" for k in range(1, 8)) + "\n")
+    for step, table in blocks:
+        t = np.asarray(table)
+        f.write(f"{int(step)} {t.shape[0]}\n")
+        for row in t:
+            f.write(f"{int(row[0])} " + " ".join(f"{v:.10g}" for v in row[1:]) + "\n")

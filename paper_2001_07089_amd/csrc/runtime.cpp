@@ -100,6 +100,7 @@ static int validate(kamd_ctx *c, const kamd_config *cfg, const kamd_replica *rep
     if (!(cfg->dt > 0.0)) return fail(c, KAMD_EINVAL, "dt must be > 0");
     if (cfg->cell_div < 0 || cfg->cell_div > 2) return fail(c, KAMD_EINVAL, "cell_div must be 0, 1 or 2");
     if (cfg->dim != 0 && cfg->dim != 2 && cfg->dim != 3) return fail(c, KAMD_EINVAL, "dim must be 0, 2 or 3");
+    if (cfg->pe_unshifted != 0 && cfg->pe_unshifted != 1) return fail(c, KAMD_EINVAL, "pe_unshifted must be 0 or 1");
     if (!(cfg->model.rc_factor > 0.0)) return fail(c, KAMD_EINVAL, "rc_factor must be > 0");
     for (int p = 0; p < 3; ++p)
         if (!(cfg->model.sigma[p] > 0.0) || !std::isfinite(cfg->model.eps[p]))
@@ -716,6 +717,8 @@ extern "C" int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replic
     c->stream = (hipStream_t)hip_stream;
     (void)hipGetDevice(&c->device);
     model_from(cfg->model, c->model, c->rc_max);
+    if (cfg->pe_unshifted)  // the energy of LAMMPS lj/cut: no V_ab(r_c) term
+        for (int p = 0; p < 3; ++p) c->model.vshift[p] = 0.0;
     int r = [&]() -> int {
         TRY(apply_list_params(c, list_skin(cfg), cfg->cell_div <= 0 ? 1 : cfg->cell_div, true));
         Plan P;

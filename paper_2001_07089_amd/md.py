@@ -59,7 +59,8 @@ class State(C.Structure):
 class Config(C.Structure):
     _fields_ = [("model", Model), ("precision", C.c_int32), ("dt", C.c_double), ("skin", C.c_double),
                 ("init_mode", C.c_int32), ("min_dist", C.c_double), ("cell_div", C.c_int32),
-                ("list_capacity", C.c_double), ("auto_sync", C.c_int32), ("dim", C.c_int32)]
+                ("list_capacity", C.c_double), ("auto_sync", C.c_int32), ("dim", C.c_int32),
+                ("pe_unshifted", C.c_int32)]
 
 
 _lib = None
@@ -130,7 +131,7 @@ def make_model(eps=KA_EPS, sigma=KA_SIGMA, rc_factor=KA_RC_FACTOR) -> Model:
 
 
 def make_config(precision="fp64", dt=0.005, skin=0.3, init_mode=INIT_GIVEN, min_dist=0.8, cell_div=1,
-                list_capacity=0.0, auto_sync=1, model=None, dim=3) -> Config:
+                list_capacity=0.0, auto_sync=1, model=None, dim=3, pe_unshifted=False) -> Config:
     c = Config()
     c.model = model if model is not None else make_model()
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -142,6 +143,7 @@ def make_config(precision="fp64", dt=0.005, skin=0.3, init_mode=INIT_GIVEN, min_
     c.list_capacity = float(list_capacity)
     c.auto_sync = int(auto_sync)
     c.dim = int(dim)
+    c.pe_unshifted = 1 if pe_unshifted else 0
     return c
 
 
@@ -320,7 +322,7 @@ class System:
 
     def __init__(self, replicas, precision="fp64", dt=0.005, skin=0.3, init="given",
                  positions=None, velocities=None, min_dist=0.8, cell_div=1, list_capacity=0.0,
-                 auto_sync=True, model=None, device="cuda", dim=3):
+                 auto_sync=True, model=None, device="cuda", dim=3, pe_unshifted=False):
         import torch
         self.torch = torch
         self.reps = make_replicas(replicas)
@@ -329,7 +331,7 @@ class System:
         self.offsets = [r.offset for r in self.reps]
         mode = {"given": INIT_GIVEN, "rsa": INIT_RSA, "lattice": INIT_LATTICE}[init]
         self.cfg = make_config(precision, dt, skin, mode, min_dist, cell_div, list_capacity,
-                               1 if auto_sync else 0, model, dim)
+                               1 if auto_sync else 0, model, dim, pe_unshifted)
         n = self.n_total
         # a dedicated stream: graph capture is not allowed on the legacy null
         # stream, and every allocation below is ordered on it

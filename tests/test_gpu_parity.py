@@ -584,3 +584,73 @@ def test_planar_rsa_init_and_rdf():
     s.step_nve(200)
     assert s.status() == 0 and np.all(s.numpy(("z",))["z"] == 0.0)
     s.close()
+
+
+# ------------------------------------------ LAMMPS conventions (Sec. IV.B, VI.A.3)
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("mixed_fixed", 1e-5)])
+def test_unshifted_energy_matches_oracle_and_forces_are_unchanged(prec, tol):
+    """pe_unshifted: the potential energy of LAMMPS lj/cut (no V_ab(r_c)
+    term) against the oracle's brute-force sum; the forces are bit for bit
+    those of the shifted configuration."""
+    n = 2000
+    log(f"case unshifted energy {prec}")
+    x, y, z, _, _, _, na, L = relaxed(n, 1.0, 3)
+    shifted = system([(n, 1.0, 3, 1.2)], prec)
+    cut = system([(n, 1.0, 3, 1.2)], prec, pe_unshifted=True)
+    o_s = shifted.forces(energy=True)
+    o_c = cut.forces(energy=True)
+    a_s = shifted.numpy(("ax", "ay", "az"))
+    a_c = cut.numpy(("ax", "ay", "az"))
+    for k in ("ax", "ay", "az"):
+        assert np.array_equal(a_s[k], a_c[k])
+    assert o_c[0, 0] == pytest.approx(O.pe_lj_cut(x, y, z, na, L), rel=max(tol, 1e-12))
+    assert o_c[0, 1] == o_s[0, 1]  # virial unchanged
+    ob_s, ob_c = shifted.observables()[0], cut.observables()[0]
+    assert ob_c[4] - ob_s[4] == pytest.approx(o_c[0, 0] - o_s[0, 0], rel=1e-12)  # E_tot moves with PE
+    shifted.close()
+    cut.close()
+
+
+def test_lammps_rdf_table_from_device_counts():
+    """compute rdf 25 bins to the force cutoff 2.5: the device counts equal the
+    oracle's, and the table (g, coordination numbers) equals the oracle's."""
+    from paper_2001_07089_amd import analysis
+    n = 3000
+    log("case lammps rdf")
+    x, y, z, _, _, _, na, L = relaxed(n, 1.0, 4)
+    s = system([(n, 1.0, 4, 1.2)], "fp64")
+    rcut, nbins = 2.5, 25
+    h = s._host(s.rdf(rcut / nbins, nbins)).astype(np.uint64)[0]
+    ref = O.rdf_hist(x, y, z, na, L, rcut / nbins, nbins)
+    assert np.array_equal(h, ref)
+    t = analysis.lammps_rdf(h, n, na, L, rcut)
+    assert np.allclose(t, O.lammps_rdf_table(ref, n, na, L, rcut, nbins), rtol=1e-13, atol=0.0)
+    # partners within 2.5: about rho_J * 4 pi 2.5^3 / 3, i.e. ~63 A and ~16 B around an A
+    assert 50.0 < t[-1, 3] < 75.0 and 10.0 < t[-1, 7] < 22.0
+    s.close()
+
+
+def test_lammps_data_file_round_trip_through_the_device():
+    """A replica written as a LAMMPS data file and read back starts a new
+    context whose forces and state equal the original bit for bit."""
+    import io
+    from paper_2001_07089_amd import lammps_io as LIO
+    n = 1500
+    log("case lammps data round trip")
+    s = system([(n, 0.8, 6, 1.2)], "mixed_fixed")
+    s.step_nve(37)
+    arr = LIO.replica_arrays(s, 0)
+    buf = io.StringIO()
+    LIO.write_data(buf, arr["x"], arr["y"], arr["z"], arr["n_a"], arr["L"], arr["vx"], arr["vy"], arr["vz"],
+                   img=arr["img"])
+    got = LIO.read_data(io.StringIO(buf.getvalue()))
+    s2 = md.System([(got["n"], got["n_a"], got["L"], 0.8, 1006)], precision="mixed_fixed",
+                   positions=(got["x"], got["y"], got["z"]), velocities=(got["vx"], got["vy"], got["vz"]))
+    s.forces()
+    s2.forces()
+    a, b = s.numpy(), s2.numpy()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+    s.close()
+    s2.close()

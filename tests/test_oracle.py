@@ -564,3 +564,65 @@ def test_planar_square_lattice_rdf():
     b = int(a / dr)
     shell = math.pi * (((b + 1) * dr) ** 2 - (b * dr) ** 2)
     assert rho * g[0, b] * shell * (n - 1) / n == pytest.approx(4.0, rel=1e-12)
+
+
+# ---------------------------------------------- LAMMPS conventions (Sec. IV.B, VI.A.3)
+
+def test_pe_lj_cut_pair_closed_forms():
+    """Two particles, one pair type at a time, placed across the periodic
+    boundary: Eq. (VKALJ) without the shift inside r_c, zero beyond."""
+    L = 10.0
+    for p, na in ((0, 2), (1, 1), (2, 0)):
+        eps, sig = O.KA_EPS[p], O.KA_SIGMA[p]
+        for r in (0.93 * sig, 1.31 * sig, 2.37 * sig, 2.61 * sig):
+            x = np.array([0.2, (0.2 - r) % L])
+            y = np.array([3.0, 3.0])
+            z = np.array([9.9, 9.9])
+            want = 4.0 * eps * ((sig / r) ** 12 - (sig / r) ** 6) if r < 2.5 * sig else 0.0
+            assert O.pe_lj_cut(x, y, z, na, L) == pytest.approx(want, rel=1e-12, abs=1e-14), (p, r)
+
+
+def test_pe_lj_cut_exceeds_the_shifted_energy_by_one_shift_per_pair():
+    """Unshifted minus shifted energy = sum over pairs inside r_c(ab) of
+    V_ab(r_c) = 4 eps_ab (0.4^12 - 0.4^6); pairs counted with a periodic k-d tree."""
+    x, y, z, na, L = _config(600, seed=5, jitter=0.2)
+    _, _, _, pe_shifted, _ = O.forces(x, y, z, na, L, "brute")
+    pe_cut = O.pe_lj_cut(x, y, z, na, L)
+    pts = np.mod(np.stack([x, y, z], axis=1), L)
+    pairs = cKDTree(pts, boxsize=L).query_pairs(2.5 * max(O.KA_SIGMA), output_type="ndarray")
+    d = pts[pairs[:, 0]] - pts[pairs[:, 1]]
+    d -= L * np.round(d / L)
+    r = np.sqrt(np.sum(d * d, axis=1))
+    p = (pairs[:, 0] >= na).astype(int) + (pairs[:, 1] >= na).astype(int)
+    sig = np.array(O.KA_SIGMA)[p]
+    inside = r < 2.5 * sig
+    shift = np.array([4.0 * e * (0.4 ** 12 - 0.4 ** 6) for e in O.KA_EPS])
+    want = float(np.sum(shift[p[inside]]))
+    assert np.count_nonzero(inside) > 1000
+    assert pe_cut - pe_shifted == pytest.approx(want, rel=1e-9)
+
+
+def test_lammps_rdf_coordination_numbers_of_a_simple_cubic_lattice():
+    """All-A simple cubic lattice: the coordination number c_AA steps through
+    the lattice shells 6 (a), 12 (a sqrt 2), 8 (a sqrt 3), 6 (2a), 24 (a sqrt 5),
+    i.e. 6, 18, 26, 32, 56, at the bins holding those radii; the g column
+    integrates back to c."""
+    m, a = 8, 1.07
+    L = m * a
+    n = m ** 3
+    i = np.arange(n)
+    x, y, z = (i % m + 0.5) * a, ((i // m) % m + 0.5) * a, (i // (m * m) + 0.5) * a
+    rcut, nbins = 2.5, 25
+    dr = rcut / nbins
+    h = O.rdf_hist(x, y, z, n, L, dr, nbins)
+    t = O.lammps_rdf_table(h, n, n, L, rcut, nbins)
+    prev = 0
+    for r, c in ((a, 6), (a * math.sqrt(2), 18), (a * math.sqrt(3), 26), (2 * a, 32), (a * math.sqrt(5), 56)):
+        b = int(r / dr)
+        assert t[b, 3] == pytest.approx(c, rel=1e-12)
+        assert t[b - 1, 3] == pytest.approx(prev, abs=1e-12)
+        prev = c
+    assert t[-1, 3] == pytest.approx(56, rel=1e-12)
+    shell = (4.0 * math.pi / 3.0) * ((t[:, 0] * dr) ** 3 - ((t[:, 0] - 1) * dr) ** 3)
+    assert np.sum(t[:, 2] * shell) * (n - 1) / L ** 3 == pytest.approx(56, rel=1e-12)
+    assert np.all(t[:, 4:] == 0.0)  # no B particles
