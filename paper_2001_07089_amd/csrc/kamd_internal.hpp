@@ -113,7 +113,8 @@ struct Dev {
     int32_t *rb_wlist;    // [nwaves]: those waves, replica by replica (set by the gate kernel)
     uint32_t *maxdisp;    // per replica: max |r - r_build|^2 (float bits) since the last check
     int32_t *nbr;         // per wave: rows x 64 entries, see list_index
-    int2 *kmax;           // per wave: rows of the A part, rows of the B part
+    int2 *kmax;           // per wave: entries of the A part, entries of the B part
+    int2 *lbase;          // per wave and part: base slot of 16-bit entries, or -1 for 32-bit entries
     int32_t *nlen;        // per slot: true list length (stats)
     // reductions
     double *wred;         // per wave [4]
@@ -176,6 +177,7 @@ hipError_t launch_ke_partial(const Dev &d, hipStream_t s);
 hipError_t launch_import(const Dev &d, const double *const *arr, const int32_t *img, hipStream_t s);
 hipError_t launch_export(const Dev &d, double *const *arr, int32_t *img, hipStream_t s);
 hipError_t launch_mirror(const Dev &d, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_store_obs(const Dev &d, double *out, hipStream_t s);

@@ -366,24 +366,55 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     uint32_t *wy = win_s[threadIdx.x / WAVE][1];
     uint32_t *wz = win_s[threadIdx.x / WAVE][2];
     const int rows = d.rows;
-    int row = 0;
+    int row = 0;  // 32-bit words of the list used so far
     int total = 0;
-    int kpart[2];
+    int kpart[2], bpart[2];
     for (int tj = 0; tj < 2; ++tj) {
         const SegInfo &SJ = d.seg[R.seg[tj]];
         const float rl2 = R.rl2_fx[S.type + tj];
         const double rp = sqrt((double)rl2) + 4096.0;  // pruning radius with margin
         const double rp2 = rp * rp;
+        // Entries of the part of the particle's own type are stored as 16-bit
+        // offsets from a base slot, two to a 32-bit word, when every slot the
+        // wavefront can accept (the cell rows of its stencils) and its own
+        // slots lie within 2^16 of the lowest of them; otherwise, and for the
+        // other part, as 32-bit slot indices.  base = -1 marks 32-bit entries.
+        int base = -1;
+        if (tj == S.type && SJ.n > 0) {
+            int lo = s, hi = s + 1;
+            if (real) {
+                // lowest and highest stencil row (qz * nc + qy) in slot order;
+                // a range that wraps around the box covers both ends
+                int z0 = cz + oz0, z1 = cz + oz0 + nz - 1;
+                if (z0 < 0 || z1 >= nc) z0 = 0, z1 = nc - 1;
+                int y0 = cy - reach, y1 = cy - reach + noff - 1;
+                if (y0 < 0 || y1 >= nc) y0 = 0, y1 = nc - 1;
+                lo = min(lo, d.cell_start[SJ.cell0 + (z0 * nc + y0) * nc]);
+                hi = max(hi, d.cell_end[SJ.cell0 + (z1 * nc + y1) * nc + nc - 1]);
+            }
+            lo = -wave_max_i(-lo);
+            hi = wave_max_i(hi);
+            if (hi - lo <= 65536) base = lo;
+        }
+        const bool half = base >= 0;
+        const int group = half ? 8 : 4;  // entries per 16-byte store
+        auto pack = [&](int a, int b) { return (a - base) | ((b - base) << 16); };
         int cnt = 0;   // entries accepted
-        int done = 0;  // entries written to the list (a multiple of 4)
-        auto flush = [&]() {  // write every complete group of four staged entries
-            while (done + 4 <= cnt) {
-                const int k = row + done;
-                const int4 q = make_int4(buf[done & (LIST_STAGE - 1)][lane], buf[(done + 1) & (LIST_STAGE - 1)][lane],
-                                         buf[(done + 2) & (LIST_STAGE - 1)][lane],
-                                         buf[(done + 3) & (LIST_STAGE - 1)][lane]);
+        int done = 0;  // entries written to the list (a multiple of group)
+        auto flush = [&]() {  // write every complete group of staged entries
+            while (done + group <= cnt) {
+                const int k = row + (half ? done / 2 : done);  // 32-bit word of the list
+                int e[8];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) e[t] = buf[(done + t) & (LIST_STAGE - 1)][lane];
+                if (half) {
+#pragma unroll
+                    for (int t = 4; t < 8; ++t) e[t] = buf[(done + t) & (LIST_STAGE - 1)][lane];
+                }
+                const int4 q = half ? make_int4(pack(e[0], e[1]), pack(e[2], e[3]), pack(e[4], e[5]), pack(e[6], e[7]))
+                                    : make_int4(e[0], e[1], e[2], e[3]);
                 if (k < rows) *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = q;
-                done += 4;
+                done += group;
             }
         };
         // Each candidate is written to the next free stage slot whether or
@@ -526,26 +557,37 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         flush();
         total += cnt;
         int kmax = wave_max_i(cnt);
-        kmax = (kmax + LIST_ROW_ALIGN - 1) / LIST_ROW_ALIGN * LIST_ROW_ALIGN;
+        const int align = half ? 2 * LIST_ROW_ALIGN : LIST_ROW_ALIGN;  // whole 16-byte words
+        kmax = (kmax + align - 1) / align * align;
         if (done < cnt) {  // the last partial group, padded with the particle's own slot
-            const int k = row + done;
-            int e[4];
+            const int k = row + (half ? done / 2 : done);
+            int e[8];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) e[t] = done + t < cnt ? buf[(done + t) & (LIST_STAGE - 1)][lane] : s;
-            if (k < rows) *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = make_int4(e[0], e[1], e[2], e[3]);
-            done += 4;
+            for (int t = 0; t < 8; ++t) e[t] = done + t < cnt ? buf[(done + t) & (LIST_STAGE - 1)][lane] : s;
+            const int4 q = half ? make_int4(pack(e[0], e[1]), pack(e[2], e[3]), pack(e[4], e[5]), pack(e[6], e[7]))
+                                : make_int4(e[0], e[1], e[2], e[3]);
+            if (k < rows) *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = q;
+            done += group;
         }
-        for (int k = row + done; k < row + kmax && k < rows; k += 4)
-            *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = make_int4(s, s, s, s);
-        if (row + kmax > rows && lane == 0) set_err(d.err, KAMD_DEV_LIST_OVERFLOW);
+        const int words = half ? kmax / 2 : kmax;  // 32-bit words the part occupies
+        const int pad = half ? pack(s, s) : s;
+        for (int k = row + (half ? done / 2 : done); k < row + words && k < rows; k += 4)
+            *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = make_int4(pad, pad, pad, pad);
+        if (row + words > rows && lane == 0) set_err(d.err, KAMD_DEV_LIST_OVERFLOW);
         kpart[tj] = kmax;
-        row += kmax;
+        bpart[tj] = base;
+        row += words;
     }
     if (row > rows) {  // keep the force kernels inside the list
-        kpart[0] = min(kpart[0], rows);
-        kpart[1] = min(kpart[1], rows - kpart[0]);
+        const int w0 = min(bpart[0] >= 0 ? kpart[0] / 2 : kpart[0], rows);
+        const int w1 = min(bpart[1] >= 0 ? kpart[1] / 2 : kpart[1], rows - w0);
+        kpart[0] = bpart[0] >= 0 ? 2 * w0 : w0;
+        kpart[1] = bpart[1] >= 0 ? 2 * w1 : w1;
     }
-    if (lane == 0) d.kmax[w] = make_int2(kpart[0], kpart[1]);
+    if (lane == 0) {
+        d.kmax[w] = make_int2(kpart[0], kpart[1]);
+        d.lbase[w] = make_int2(bpart[0], bpart[1]);
+    }
     d.nlen[s] = real ? total - 1 : 0;  // partners, without the own slot
 }
 

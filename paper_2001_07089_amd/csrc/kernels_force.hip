@@ -53,6 +53,29 @@ __device__ inline double rcp_f64(double a)
     return fma(y, e, y);
 }
 
+// Entries k .. k+3 of a list part (k a multiple of 4).  32-bit entries fill
+// a 16-byte word.  16-bit entries (offsets from base) fill half of one, and
+// the next four are the other half of the same word (a cache hit), so that
+// both formats gather four neighbours per pass.
+__device__ inline void list_quad32(const int4 *nb, int k, int jj[4])
+{
+    const int4 q = nb[(k >> 2) * WAVE];
+    jj[0] = q.x;
+    jj[1] = q.y;
+    jj[2] = q.z;
+    jj[3] = q.w;
+}
+__device__ inline void list_quad16(const int4 *nb, int k, int base, int jj[4])
+{
+    const int4 q = nb[(k >> 3) * WAVE];
+    const bool hi = (k & 4) != 0;
+    const uint32_t a = (uint32_t)(hi ? q.z : q.x), b = (uint32_t)(hi ? q.w : q.y);
+    jj[0] = base + (int)(a & 0xffffu);
+    jj[1] = base + (int)(a >> 16);
+    jj[2] = base + (int)(b & 0xffffu);
+    jj[3] = base + (int)(b >> 16);
+}
+
 template <bool ENERGY>
 __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_inc)
 {
@@ -65,25 +88,22 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
     const double L = R.L, invL = R.invL;
     const double xi = d.x[s], yi = d.y[s], zi = d.z[s];
     const int2 km = d.kmax[w];
+    const int2 lb = d.lbase[w];
     double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, vir = 0.0, npair = 0.0;
-    int row = 0;
+    int row = 0;  // 32-bit words of the list
 #pragma unroll 1
     for (int tj = 0; tj < 2; ++tj) {
         const int p = S.type + tj;
         const double rc2 = m.rc2[p], sig2 = m.sig2[p];
         const int nrows = tj ? km.y : km.x;
+        const int base = tj ? lb.y : lb.x;
         double sx = 0.0, sy = 0.0, sz = 0.0, se = 0.0, sv = 0.0;
         int cnt = 0;
         const int4 *nb = reinterpret_cast<const int4 *>(d.nbr + list_index(w, d.rows, row, lane_id()));
-        for (int k = 0; k < nrows; k += 4) {
-            const int4 q = nb[(k >> 2) * WAVE];
-            const int jj[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int j = jj[u];
-                double dx = xi - d.x[j];
-                double dy = yi - d.y[j];
-                double dz = zi - d.z[j];
+        auto pair = [&](double xj, double yj, double zj) {
+                double dx = xi - xj;
+                double dy = yi - yj;
+                double dz = zi - zj;
                 dx = fma(-L, rint(dx * invL), dx);
                 dy = fma(-L, rint(dy * invL), dy);
                 dz = fma(-L, rint(dz * invL), dz);
@@ -102,6 +122,29 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
                     sv += t;
                     cnt += in ? 1 : 0;
                 }
+        };
+        auto quad = [&](const int jj[4]) {
+            double xj[4], yj[4], zj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xj[u] = d.x[jj[u]];
+                yj[u] = d.y[jj[u]];
+                zj[u] = d.z[jj[u]];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pair(xj[u], yj[u], zj[u]);
+        };
+        if (base >= 0) {
+            for (int k = 0; k < nrows; k += 4) {
+                int jj[4];
+                list_quad16(nb, k, base, jj);
+                quad(jj);
+            }
+        } else {
+            for (int k = 0; k < nrows; k += 4) {
+                int jj[4];
+                list_quad32(nb, k, jj);
+                quad(jj);
             }
         }
         const double e48 = 48.0 * m.eps[p];
@@ -113,7 +156,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
             vir += 0.5 * e48 * sv;
             npair += (double)cnt;
         }
-        row += nrows;
+        row += base >= 0 ? nrows / 2 : nrows;
     }
     d.ax[s] = fx;
     d.ay[s] = fy;
@@ -152,24 +195,21 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
     const int s = w * WAVE + lane_id();
     const uint4 mi = d.mirror[s];
     const int2 km = d.kmax[w];
+    const int2 lb = d.lbase[w];
     double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, vir = 0.0, npair = 0.0;
     uint64_t qx = 0, qy = 0, qz = 0;
-    int row = 0;
+    int row = 0;  // 32-bit words of the list
 #pragma unroll 1
     for (int tj = 0; tj < 2; ++tj) {
         const int p = S.type + tj;
         const float rc2 = R.rc2_fx[p], sig2 = R.sig2_fx[p];
         const double fk = R.fix_k[p];
         const int nrows = tj ? km.y : km.x;
+        const int base = tj ? lb.y : lb.x;
         float sx = 0.0f, sy = 0.0f, sz = 0.0f, se = 0.0f, sv = 0.0f;
         int cnt = 0;
         const int4 *nb = reinterpret_cast<const int4 *>(d.nbr + list_index(w, d.rows, row, lane_id()));
-        for (int k = 0; k < nrows; k += 4) {
-            const int4 q = nb[(k >> 2) * WAVE];
-            const int jj[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const uint4 mj = d.mirror[jj[u]];
+        auto pair = [&](const uint4 mj) {
                 const int ix = (int)(mi.x - mj.x);
                 const int iy = (int)(mi.y - mj.y);
                 const int iz = (int)(mi.z - mj.z);
@@ -196,6 +236,25 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
                     sv += t;
                     cnt += in ? 1 : 0;
                 }
+        };
+        auto quad = [&](const int jj[4]) {
+            uint4 mj[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) mj[u] = d.mirror[jj[u]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pair(mj[u]);
+        };
+        if (base >= 0) {
+            for (int k = 0; k < nrows; k += 4) {
+                int jj[4];
+                list_quad16(nb, k, base, jj);
+                quad(jj);
+            }
+        } else {
+            for (int k = 0; k < nrows; k += 4) {
+                int jj[4];
+                list_quad32(nb, k, jj);
+                quad(jj);
             }
         }
         if (FIXED) {
@@ -214,7 +273,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
             vir += 0.5 * 48.0 * m.eps[p] * (double)sv;
             npair += (double)cnt;
         }
-        row += nrows;
+        row += base >= 0 ? nrows / 2 : nrows;
     }
     if (FIXED) {
         const double inv = 1.0 / FIX_SCALE;

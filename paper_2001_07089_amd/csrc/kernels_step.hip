@@ -358,10 +358,10 @@ __global__ __launch_bounds__(BLOCK) void k_mirror(Dev d)
     d.mirror[c.s] = make_uint4(to_fix(d.x[c.s], invL), to_fix(d.y[c.s], invL), to_fix(d.z[c.s], invL), 0u);
 }
 
-__global__ void k_zero_i32(int32_t *p, int64_t n)
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
+        p[i] = v;
 }
 __global__ void k_zero_f64(double *p, int64_t n)
 {
@@ -483,13 +483,14 @@ hipError_t launch_mirror(const Dev &d, hipStream_t s)
     hipLaunchKernelGGL(k_mirror, dim3(nblk(d)), dim3(BLOCK), 0, s, d);
     return hipGetLastError();
 }
-hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s)
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;
     int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_zero_i32, dim3(nb), dim3(256), 0, s, p, n);
+    hipLaunchKernelGGL(k_fill_i32, dim3(nb), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s) { return launch_fill_i32(p, n, 0, s); }
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s)
 {
     if (n <= 0) return hipSuccess;

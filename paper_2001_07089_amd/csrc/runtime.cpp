@@ -251,7 +251,7 @@ static size_t plan_bytes(const Plan &P, int n_rep)
     b += 4 * np;                               // nlen
     b += 4 * (size_t)P.ncells_wide * 3;        // count/start/end
     b += 4 * (size_t)P.rows * np;              // neighbour list
-    b += (8 + 4 + 32) * (size_t)P.nwaves;      // kmax, disp, wred
+    b += (8 + 8 + 4 + 32) * (size_t)P.nwaves;  // kmax, lbase, disp, wred
     b += (sizeof(SegInfo) + sizeof(RepInfo)) * 2 * (size_t)n_rep + 4 * ((size_t)P.nwaves + P.ncells_wide);
     b += 3 * 8 * nt;                           // one MSD origin (more on demand)
     b += 8 * (size_t)n_rep;                    // per-replica kernel arguments
@@ -427,6 +427,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     d.maxdisp = c->md_base;
     TRY(dalloc(c, &c->mirror_alt, np));
     TRY(dalloc(c, &d.kmax, P.nwaves));
+    TRY(dalloc(c, &d.lbase, P.nwaves));
     TRY(dalloc(c, &d.wred, 4 * (size_t)P.nwaves));
     TRY(dalloc(c, &d.rsum, 4 * (size_t)d.nrep));
     TRY(dalloc(c, &d.obs, 8 * (size_t)d.nrep));
@@ -448,6 +449,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     HIPCHK(c, launch_zero_i32((int32_t *)c->md_base, 2 * (int64_t)d.nrep, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)c->mirror_alt, 4 * np, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)d.kmax, 2 * (int64_t)P.nwaves, c->stream));
+    HIPCHK(c, launch_fill_i32((int32_t *)d.lbase, 2 * (int64_t)P.nwaves, -1, c->stream));
     HIPCHK(c, launch_zero_f64(d.wred, 4 * (int64_t)P.nwaves, c->stream));
     HIPCHK(c, launch_zero_f64((double *)d.dyn, 8 * (int64_t)d.nrep, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)d.err, 4, c->stream));
