@@ -111,12 +111,14 @@ def timed_graph(s, md, torch, steps):
 # reads x,y,z,vx,vy,vz (48), the image counters (12), the u32 mirror (16) and
 # the mirror at the last list build (16), and writes x..vz (48), the image
 # counters (12) and the next mirror (16); the FP64 force-only kernel reads
-# x,y,z (24) and writes ax,ay,az (24).  Each list entry is a 4-byte index.
+# x,y,z (24) and writes ax,ay,az (24).  The list adds its stored size: a
+# 4-byte index per entry, or a 2-byte offset where the part of the list is
+# stored in 16 bits (md_stats mean_list_bytes, without wavefront padding).
 STATE_BYTES = {"mixed": 168, "mixed_fixed": 168, "fp64": 48}
 
 
-def algorithmic_bytes(mean_list_len, n, precision):
-    return n * (4.0 * mean_list_len + STATE_BYTES[precision])
+def algorithmic_bytes(mean_list_bytes, n, precision):
+    return n * (mean_list_bytes + STATE_BYTES[precision])
 
 
 def kernel_name(precision):
@@ -407,7 +409,7 @@ def main():
     achieved = flops / (prof["force_ms"] * 1e-3) / 1e12
     candidates = st["mean_list_len"] * n
     traffic = stored_traffic(skin, int(st["cell_div"]), a.precision, n)
-    alg = algorithmic_bytes(st["mean_list_len"], n, a.precision)
+    alg = algorithmic_bytes(st["mean_list_bytes"], n, a.precision)
     gbs = alg / (prof["force_ms"] * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK, "unit": "GB/s", "frac": gbs / HBM_PEAK,
             "traffic": traffic, "kernel": kernel_name(a.precision), "kernel_ms": prof["force_ms"],

@@ -276,8 +276,11 @@ int md_autotune(kamd_ctx *ctx, int32_t probe_steps, double *host_out);
 /* Change skin and cell division (forces a rebuild at the next step). */
 int md_set_list_params(kamd_ctx *ctx, double skin, int32_t cell_div);
 
-/* Statistics: host_out (host, FP64 [8]) = {steps, rebuilds, n_total,
- * list_rows, mean_list_len, max_list_len, skin, cell_div}.  Syncs. */
+/* Statistics: host_out (host, FP64 [9]) = {steps, rebuilds, n_total,
+ * list_rows, mean_list_len, max_list_len, skin, cell_div, mean_list_bytes}.
+ * List lengths count partners at the last build (without wavefront padding);
+ * mean_list_bytes is their stored size per particle (4 bytes per 32-bit entry,
+ * 2 per 16-bit entry).  Syncs. */
 int md_stats(kamd_ctx *ctx, double *host_out);
 
 /* Checkpoint: the full dynamical state (positions, velocities, forces, image

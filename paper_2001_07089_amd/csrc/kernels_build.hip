@@ -369,6 +369,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     int row = 0;  // 32-bit words of the list used so far
     int total = 0;
     int kpart[2], bpart[2];
+    int n16 = 0;
     for (int tj = 0; tj < 2; ++tj) {
         const SegInfo &SJ = d.seg[R.seg[tj]];
         const float rl2 = R.rl2_fx[S.type + tj];
@@ -576,6 +577,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         if (row + words > rows && lane == 0) set_err(d.err, KAMD_DEV_LIST_OVERFLOW);
         kpart[tj] = kmax;
         bpart[tj] = base;
+        if (half) n16 = cnt - 1;  // 16-bit partner entries (the own slot is one of the cnt)
         row += words;
     }
     if (row > rows) {  // keep the force kernels inside the list
@@ -588,7 +590,9 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         d.kmax[w] = make_int2(kpart[0], kpart[1]);
         d.lbase[w] = make_int2(bpart[0], bpart[1]);
     }
-    d.nlen[s] = real ? total - 1 : 0;  // partners, without the own slot
+    // partners (without the own slot) in the low 16 bits, those of them
+    // stored as 16-bit entries in the high 16 bits
+    d.nlen[s] = real ? (total - 1) | (n16 << 16) : 0;
 }
 
 static inline int nblk_slots(const Dev &d) { return (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }

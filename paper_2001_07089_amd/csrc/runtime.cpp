@@ -1073,10 +1073,16 @@ extern "C" int md_stats(kamd_ctx *c, double *host_out)
     HIPCHK(c, hipMemcpyAsync(nlen.data(), c->d.nlen, 4 * nlen.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(id.data(), c->d.id, 4 * id.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double sum = 0.0, mx = 0.0;
+    double sum = 0.0, mx = 0.0, bytes = 0.0;
     int64_t cntr = 0;
     for (size_t i = 0; i < nlen.size(); ++i)
-        if (id[i] >= 0) { sum += nlen[i]; mx = std::max(mx, (double)nlen[i]); ++cntr; }
+        if (id[i] >= 0) {
+            const int partners = nlen[i] & 0xffff, n16 = (nlen[i] >> 16) & 0xffff;
+            sum += partners;
+            bytes += 4.0 * (partners - n16) + 2.0 * n16;
+            mx = std::max(mx, (double)partners);
+            ++cntr;
+        }
     host_out[0] = (double)c->step;
     host_out[1] = (double)cnt[0];
     host_out[2] = (double)c->d.n_total;
@@ -1085,6 +1091,7 @@ extern "C" int md_stats(kamd_ctx *c, double *host_out)
     host_out[5] = mx;
     host_out[6] = c->skin;
     host_out[7] = (double)c->cell_div;
+    host_out[8] = cntr ? bytes / cntr : 0.0;
     return KAMD_OK;
 }
 

@@ -275,9 +275,10 @@ def md_set_list_params(ctx, skin: float, cell_div: int):
 
 
 def md_stats(ctx):
-    out = np.zeros(8)
+    out = np.zeros(9)
     _check(lib().md_stats(ctx, out.ctypes.data), ctx)
-    keys = ("steps", "rebuilds", "n_total", "list_rows", "mean_list_len", "max_list_len", "skin", "cell_div")
+    keys = ("steps", "rebuilds", "n_total", "list_rows", "mean_list_len", "max_list_len", "skin", "cell_div",
+            "mean_list_bytes")
     return dict(zip(keys, out.tolist()))
 
 

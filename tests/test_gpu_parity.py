@@ -654,3 +654,19 @@ def test_lammps_data_file_round_trip_through_the_device():
         assert np.array_equal(a[k], b[k]), k
     s.close()
     s2.close()
+
+
+def test_list_statistics_count_16bit_entries():
+    """A 2000-particle box has fewer than 2^16 slots per type segment, so the
+    own-type part of every list is stored in 16 bits and the other part in
+    32: about 0.8 * 2 + 0.2 * 4 bytes per partner for A particles and
+    0.2 * 2 + 0.8 * 4 for B, 2.6 on average."""
+    log("case list statistics")
+    s = system([(2000, 1.0, 3, 1.2)], "mixed_fixed")
+    s.forces()
+    st = md.md_stats(s.ctx)
+    ratio = st["mean_list_bytes"] / st["mean_list_len"]
+    log(f"  bytes per partner {ratio:.3f}")
+    assert 2.3 < ratio < 3.0
+    assert st["max_list_len"] <= st["list_rows"]
+    s.close()
