@@ -18,6 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OUTDIR = os.path.join(HERE, "_lib")
 OBJDIR = os.path.join(ROOT, "_build", "kamd")
 LIB = os.path.join(OUTDIR, "libkamd.so")
+# the compiler's per-kernel resource report (registers, scratch, occupancy)
+RESOURCES = os.path.join(ROOT, "_build", "kamd", "kernel_resources.txt")
 
 SOURCES = {
     "kernels_build.hip": [],
@@ -44,7 +46,8 @@ def common_flags():
 def _compile(src, extra):
     obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [hipcc()] + common_flags() + extra + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    report = ["-Rpass-analysis=kernel-resource-usage"] if src.endswith(".hip") else []
+    cmd = [hipcc()] + common_flags() + extra + lang + report + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
@@ -58,11 +61,15 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(5, os.cpu_count() or 1)) as ex:
         futs = [ex.submit(_compile, s, e) for s, e in SOURCES.items()]
         objs = []
+        report = []
         for f in futs:
             obj, log = f.result()
             objs.append(obj)
+            report += [ln for ln in log.splitlines() if "remark:" in ln]
             if verbose and log.strip():
-                print(log, file=sys.stderr)
+                print("\n".join(ln for ln in log.splitlines() if "remark:" not in ln), file=sys.stderr)
+    with open(RESOURCES, "w") as fh:
+        fh.write("\n".join(report) + "\n")
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -399,10 +399,10 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         }
         const bool half = base >= 0;
         const int group = half ? 8 : 4;  // entries per 16-byte store
-        auto pack = [&](int a, int b) { return (a - base) | ((b - base) << 16); };
+        auto pack = [&](int a, int b) __attribute__((always_inline)) { return (a - base) | ((b - base) << 16); };
         int cnt = 0;   // entries accepted
         int done = 0;  // entries written to the list (a multiple of group)
-        auto flush = [&]() {  // write every complete group of staged entries
+        auto flush = [&]() __attribute__((always_inline)) {  // write every complete group of staged entries
             while (done + group <= cnt) {
                 const int k = row + (half ? done / 2 : done);  // 32-bit word of the list
                 int e[8];
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         // The particle's own slot passes the test (zero separation) and stays
         // in its list, where the force kernels skip it like the padding.
         // `in` is false only past the end of a range, in the last batch.
-        auto test = [&](int j, bool in, uint32_t jx, uint32_t jy, uint32_t jz) {
+        auto test = [&](int j, bool in, uint32_t jx, uint32_t jy, uint32_t jz) __attribute__((always_inline)) {
             const float dx = (float)(int)(mi.x - jx);
             const float dy = (float)(int)(mi.y - jy);
             const float dz = (float)(int)(mi.z - jz);
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             buf[cnt & (LIST_STAGE - 1)][lane] = j;
             cnt += acc;
         };
-        auto scan = [&](int st, int en) {  // straight from global memory
+        auto scan = [&](int st, int en) __attribute__((always_inline)) {  // straight from global memory
             int j = st;
             for (; j + LIST_UNROLL <= en; j += LIST_UNROLL) {  // whole batches
                 const uint4 *src = d.smirror + j;
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             }
             if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
         };
-        auto scan_staged = [&](int st, int en) {  // all lanes of the wavefront take part
+        auto scan_staged = [&](int st, int en) __attribute__((always_inline)) {  // all lanes of the wavefront take part
             const bool has = st < en;
             const int lo = -wave_max_i(has ? -st : INT_MIN + 1);
             if (lo == INT_MAX) return;
