@@ -22,6 +22,8 @@ constexpr int WAVE = 64;
 constexpr int BLOCK = 256;               // threads per block for slot kernels
 constexpr int WAVES_PER_BLOCK = BLOCK / WAVE;
 constexpr int LIST_ROW_ALIGN = 4;        // neighbour rows are padded to this multiple
+constexpr int CELL_SUBX = 4;             // list cells are sorted in sub-cells of a quarter
+                                         // cell edge along x (cell_count/start/end per sub-cell)
 constexpr int VH_MAX_BINS = 1024;       // bins of the self van Hove histogram
 constexpr int LIST_UNROLL = 8;           // candidates per step of the list builder's scan
 

@@ -120,7 +120,8 @@ __device__ inline void assign_wave(const Dev &d, int w)
     if (real) {
         const uint4 m = d.mirror[s];
         const int cz = d.dim == 2 ? 0 : fix_cell(m.z, nc);  // planar: one layer of cells
-        c = S.cell0 + (cz * nc + fix_cell(m.y, nc)) * nc + fix_cell(m.x, nc);
+        // sub-cell: the cell, then the quarter of its edge along x
+        c = CELL_SUBX * (S.cell0 + (cz * nc + fix_cell(m.y, nc)) * nc) + fix_cell(m.x, CELL_SUBX * nc);
         d.cell_of[s] = c;
     }
     // Runs of consecutive lanes with the same cell (the slots are still in the
@@ -148,10 +149,14 @@ __global__ __launch_bounds__(BLOCK) void k_rb_assign(Dev d)
         assign_wave(d, d.rb_wlist[i]);
 }
 
-// Exclusive scan of one segment's cell counters into absolute slot ranges
-// [cell_start, cell_end).  One block of 1024 threads per segment; each pass
-// scans 8192 counters (8 consecutive per thread, wavefront shuffles, then the
-// 16 wavefront totals).
+// Exclusive scan of one segment's sub-cell counters into absolute slot
+// ranges [cell_start, cell_end).  One block of 1024 threads per segment; each
+// pass covers 8192 cells (8 consecutive per thread, wavefront shuffles, then
+// the 16 wavefront totals).  A cell's CELL_SUBX = 4 sub-cell counters are
+// read as one int4 and its ranges written as int4s, so a pass moves no more
+// loads and stores than a scan of the cells alone would.
+static_assert(CELL_SUBX == 4, "the scan reads the sub-cells of a cell as one int4");
+
 __global__ __launch_bounds__(1024) void k_rb_scan(Dev d)
 {
     __shared__ int wtot[16];
@@ -166,15 +171,17 @@ __global__ __launch_bounds__(1024) void k_rb_scan(Dev d)
     }
     __syncthreads();
     const int n = S.ncell;
-    const int32_t *cnt = d.cell_count + S.cell0;
+    const int4 *cnt = reinterpret_cast<const int4 *>(d.cell_count + CELL_SUBX * S.cell0);
+    int4 *cst = reinterpret_cast<int4 *>(d.cell_start + CELL_SUBX * S.cell0);
+    int4 *cen = reinterpret_cast<int4 *>(d.cell_end + CELL_SUBX * S.cell0);
     for (int base = 0; base < n; base += 8192) {
-        int v[8];
+        int4 v[8];
         int sum = 0;
         const int i0 = base + 8 * t;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            v[k] = (i0 + k < n) ? cnt[i0 + k] : 0;
-            sum += v[k];
+            v[k] = (i0 + k < n) ? cnt[i0 + k] : make_int4(0, 0, 0, 0);
+            sum += v[k].x + v[k].y + v[k].z + v[k].w;
         }
         int inc = sum;  // inclusive scan over the wavefront
 #pragma unroll
@@ -193,9 +200,13 @@ __global__ __launch_bounds__(1024) void k_rb_scan(Dev d)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             if (i0 + k < n) {
-                d.cell_start[S.cell0 + i0 + k] = run;
-                run += v[k];
-                d.cell_end[S.cell0 + i0 + k] = run;
+                int4 a, b;
+                a.x = run; run += v[k].x; b.x = run;
+                a.y = run; run += v[k].y; b.y = run;
+                a.z = run; run += v[k].z; b.z = run;
+                a.w = run; run += v[k].w; b.w = run;
+                cst[i0 + k] = a;
+                cen[i0 + k] = b;
             }
         }
         __syncthreads();
@@ -236,31 +247,52 @@ __device__ inline void gather_one(const Dev &d, int v, int t)
     d.smirror[t] = d.mirror[v];
 }
 
-// One wavefront per cell.  The destination of each member is its rank by
-// previous slot, which makes the counting sort stable.  Cells of up to 64
+// One wavefront per cell.  The members of the cell are grouped by sub-cell
+// (the scatter put them there); the destination of each member is its
+// sub-cell's start plus its rank by previous slot among the members of the
+// same sub-cell, which makes the counting sort stable.  Cells of up to 64
 // members rank in registers; larger ones (only tiny boxes with 1-2 cells per
 // edge) fall back to a loop over memory.
 __device__ inline void sortgather_cell(const Dev &d, int c)
 {
     const SegInfo &S = d.seg[d.cell_seg[c]];
     if (!rebuild_flag(d, S.rep)) return;
-    const int st = d.cell_start[c];
-    const int m = d.cell_end[c] - st;
+    const int c0 = CELL_SUBX * c;
+    const int st = d.cell_start[c0];
+    const int m = d.cell_end[c0 + CELL_SUBX - 1] - st;
+    int bnd[CELL_SUBX];  // start of each sub-cell
+#pragma unroll
+    for (int k = 0; k < CELL_SUBX; ++k) bnd[k] = d.cell_start[c0 + k];
+    auto sub_of = [&](int p) __attribute__((always_inline)) {
+        int k = 0;
+#pragma unroll
+        for (int t = 1; t < CELL_SUBX; ++t) k += p >= bnd[t] ? 1 : 0;
+        return k;
+    };
     const int lane = lane_id();
     if (m <= WAVE) {
         const int v = lane < m ? d.order[st + lane] : 0x7fffffff;
+        const int k = sub_of(st + lane);
         int rank = 0;
-        for (int e2 = 0; e2 < m; ++e2) rank += (__shfl(v, e2, 64) < v) ? 1 : 0;
-        if (lane < m) gather_one(d, v, st + rank);
+        for (int e2 = 0; e2 < m; ++e2)
+            rank += (__shfl(k, e2, 64) == k && __shfl(v, e2, 64) < v) ? 1 : 0;
+        int b = bnd[0];
+#pragma unroll
+        for (int t = 1; t < CELL_SUBX; ++t) b = k == t ? bnd[t] : b;
+        if (lane < m) gather_one(d, v, b + rank);
     } else {
         for (int e = lane; e < m; e += WAVE) {
             const int v = d.order[st + e];
+            const int k = sub_of(st + e);
             int rank = 0;
-            for (int e2 = 0; e2 < m; ++e2) rank += (d.order[st + e2] < v) ? 1 : 0;
-            gather_one(d, v, st + rank);
+            for (int e2 = 0; e2 < m; ++e2) rank += (sub_of(st + e2) == k && d.order[st + e2] < v) ? 1 : 0;
+            int b = bnd[0];
+#pragma unroll
+            for (int t = 1; t < CELL_SUBX; ++t) b = k == t ? bnd[t] : b;
+            gather_one(d, v, b + rank);
         }
     }
-    if (lane == 0) d.cell_count[c] = 0;  // ready for the next rebuild
+    if (lane < CELL_SUBX) d.cell_count[c0 + lane] = 0;  // ready for the next rebuild
 }
 
 __global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
@@ -355,7 +387,12 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     const int noff = min(nc, 2 * reach + 1);
     const bool whole = nc < 2 * reach + 1;  // every cell of a row is in the stencil
     const bool prune = !whole && reach > 1;
-    const int cx = fix_cell(mi.x, nc), cy = fix_cell(mi.y, nc), cz = d.dim == 2 ? 0 : fix_cell(mi.z, nc);
+    const int fx = fix_cell(mi.x, CELL_SUBX * nc);  // x in quarter cells
+    const int cx = fx / CELL_SUBX, qx = fx % CELL_SUBX;
+    const int cy = fix_cell(mi.y, nc), cz = d.dim == 2 ? 0 : fix_cell(mi.z, nc);
+    // slot range [cs(c), ce(c)) of cell c (its sub-cells together)
+    auto cs = [&](int c) __attribute__((always_inline)) { return d.cell_start[CELL_SUBX * c]; };
+    auto ce = [&](int c) __attribute__((always_inline)) { return d.cell_end[CELL_SUBX * c + CELL_SUBX - 1]; };
     // a planar system has every particle in its single (z = 0) layer of cells
     const int oz0 = d.dim == 2 ? 0 : -reach, nz = d.dim == 2 ? 1 : noff;
     const double cw = 4294967296.0 / (double)nc;  // cell edge in fixed units
@@ -390,8 +427,8 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                 if (z0 < 0 || z1 >= nc) z0 = 0, z1 = nc - 1;
                 int y0 = cy - reach, y1 = cy - reach + noff - 1;
                 if (y0 < 0 || y1 >= nc) y0 = 0, y1 = nc - 1;
-                lo = min(lo, d.cell_start[SJ.cell0 + (z0 * nc + y0) * nc]);
-                hi = max(hi, d.cell_end[SJ.cell0 + (z1 * nc + y1) * nc + nc - 1]);
+                lo = min(lo, cs(SJ.cell0 + (z0 * nc + y0) * nc));
+                hi = max(hi, ce(SJ.cell0 + (z1 * nc + y1) * nc + nc - 1));
             }
             lo = -wave_max_i(-lo);
             hi = wave_max_i(hi);
@@ -512,13 +549,13 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                         }
                         const int a = cx + xl, b = cx + xr;  // unwrapped cell range [a, b]
                         if (a < 0) {
-                            scan(d.cell_start[rowc + a + nc], d.cell_end[rowc + nc - 1]);
-                            scan(d.cell_start[rowc], d.cell_end[rowc + b]);
+                            scan(cs(rowc + a + nc), ce(rowc + nc - 1));
+                            scan(cs(rowc), ce(rowc + b));
                         } else if (b >= nc) {
-                            scan(d.cell_start[rowc + a], d.cell_end[rowc + nc - 1]);
-                            scan(d.cell_start[rowc], d.cell_end[rowc + b - nc]);
+                            scan(cs(rowc + a), ce(rowc + nc - 1));
+                            scan(cs(rowc), ce(rowc + b - nc));
                         } else {
-                            scan(d.cell_start[rowc + a], d.cell_end[rowc + b]);
+                            scan(cs(rowc + a), ce(rowc + b));
                         }
                     }
                 }
@@ -533,19 +570,25 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                     int s0 = 0, e0 = 0, s1 = 0, e1 = 0, s2 = 0, e2 = 0;
                     if (real) {
                         if (whole) {
-                            s1 = d.cell_start[rowc];
-                            e1 = d.cell_end[rowc + nc - 1];
+                            s1 = cs(rowc);
+                            e1 = ce(rowc + nc - 1);
                         } else {
+                            // One cell per list radius (reach 1): a particle in
+                            // quarter qx of its cell is more than a cell edge,
+                            // and so more than the list radius, away along x
+                            // from the quarters of the left cell below qx and
+                            // of the right cell above qx; both are left out.
                             const int a = cx - reach, b = cx + reach;
-                            if (a < 0) {
-                                s0 = d.cell_start[rowc + a + nc];
-                                e0 = d.cell_end[rowc + nc - 1];
+                            const int32_t *cstart = d.cell_start, *cend = d.cell_end;
+                            if (a < 0) {  // the left cell wraps to the high end
+                                s0 = cstart[CELL_SUBX * (rowc + a + nc) + qx];
+                                e0 = cend[CELL_SUBX * (rowc + nc) - 1];
                             }
-                            s1 = d.cell_start[rowc + max(a, 0)];
-                            e1 = d.cell_end[rowc + min(b, nc - 1)];
-                            if (b >= nc) {
-                                s2 = d.cell_start[rowc];
-                                e2 = d.cell_end[rowc + b - nc];
+                            s1 = cstart[a < 0 ? CELL_SUBX * rowc : CELL_SUBX * (rowc + a) + qx];
+                            e1 = cend[b >= nc ? CELL_SUBX * (rowc + nc) - 1 : CELL_SUBX * (rowc + b) + qx];
+                            if (b >= nc) {  // the right cell wraps to the low end
+                                s2 = cstart[CELL_SUBX * rowc];
+                                e2 = cend[CELL_SUBX * (rowc + b - nc) + qx];
                             }
                         }
                     }

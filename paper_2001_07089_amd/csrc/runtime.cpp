@@ -132,10 +132,11 @@ struct Plan {
 
 // Limits of the list cell grid.  A segment holds at most 2^24 cells (nc is
 // lowered to fit: wider cells stay correct, they only add candidates), and a
-// plan at most 2^28 cells in all, which keeps every cell index, scan offset
-// and launch size far inside 32 bits.
+// plan at most 2^26 cells in all (52 bytes each with the sub-cell counters
+// and ranges), which keeps every sub-cell index, scan offset and launch size
+// far inside 32 bits.
 constexpr int64_t MAX_SEG_CELLS = (int64_t)1 << 24;
-constexpr int64_t MAX_PLAN_CELLS = (int64_t)1 << 28;
+constexpr int64_t MAX_PLAN_CELLS = (int64_t)1 << 26;
 
 static int cell_cap(int dim) { return dim == 2 ? 4096 : 256; }  // nc^(dim) <= MAX_SEG_CELLS
 
@@ -249,7 +250,7 @@ static size_t plan_bytes(const Plan &P, int n_rep)
     b += 16 * np + 16 * LIST_UNROLL;           // mbuild, tail of the sorted mirror
     b += 4 * np * 3;                           // cell_of, rank, order
     b += 4 * np;                               // nlen
-    b += 4 * (size_t)P.ncells_wide * 3;        // count/start/end
+    b += 4 * (size_t)P.ncells_wide * 3 * CELL_SUBX;  // count/start/end per sub-cell
     b += 4 * (size_t)P.rows * np;              // neighbour list
     b += (8 + 8 + 4 + 32) * (size_t)P.nwaves;  // kmax, lbase, disp, wred
     b += (sizeof(SegInfo) + sizeof(RepInfo)) * 2 * (size_t)n_rep + 4 * ((size_t)P.nwaves + P.ncells_wide);
@@ -365,9 +366,10 @@ static int alloc_list_buffers(kamd_ctx *c, const Plan &P)
     dfree(c, c->nbr_alloc);
     c->nbr_alloc = nullptr;
     int32_t *cc, *cs, *ce, *csg;
-    TRY(dalloc(c, &cc, P.ncells));
-    TRY(dalloc(c, &cs, P.ncells));
-    TRY(dalloc(c, &ce, P.ncells));
+    const size_t nsub = (size_t)CELL_SUBX * P.ncells;  // counters and ranges per sub-cell
+    TRY(dalloc(c, &cc, nsub));
+    TRY(dalloc(c, &cs, nsub));
+    TRY(dalloc(c, &ce, nsub));
     TRY(dalloc(c, &csg, P.ncells));
     c->cells_alloc[0] = cc;
     c->cells_alloc[1] = cs;
@@ -383,7 +385,7 @@ static int alloc_list_buffers(kamd_ctx *c, const Plan &P)
     d.nbr = nb;
     d.rows = P.rows;
     d.ncells = P.ncells;
-    HIPCHK(c, launch_zero_i32(cc, P.ncells, c->stream));
+    HIPCHK(c, launch_zero_i32(cc, (int64_t)nsub, c->stream));
     HIPCHK(c, launch_zero_i32(nb, (int64_t)P.rows * P.npad, c->stream));
     return KAMD_OK;
 }

@@ -75,22 +75,23 @@ def test_planar_cell_grid_is_one_layer():
     one = md.md_workspace_size(md.make_config(precision="mixed_fixed", dim=2, cell_div=1), reps)
     two = md.md_workspace_size(md.make_config(precision="mixed_fixed", dim=2, cell_div=2), reps)
     assert one < 1 << 30 and two < 1 << 30
-    # division 1: 2 * 333^2 cells; division 2: 2 * 666^2; 16 bytes per cell
-    assert abs(two - one) < 16 * 2 * 700 ** 2
+    # division 1: 2 * 333^2 cells; division 2: 2 * 666^2; 52 bytes per cell
+    # (count, start and end for each of 4 sub-cells, and the segment index)
+    assert abs(two - one) < 52 * 2 * 700 ** 2
 
 
 def test_cell_grid_limits():
     """Cells per edge are capped (wider cells stay correct), and a plan whose
-    cell grid would exceed 2^28 cells in all is refused, not truncated."""
+    cell grid would exceed 2^26 cells in all is refused, not truncated."""
     cfg = md.make_config()
-    sparse = [(1000, 800, 800.0, 1.0, 3 + i) for i in range(9)]  # 2 * 256^3 cells each after the cap
-    eight = md.md_workspace_size(cfg, md.make_replicas(sparse[:8]))
-    assert eight < 16 * (1 << 28) + (1 << 28)
+    sparse = [(1000, 800, 800.0, 1.0, 3 + i) for i in range(3)]  # 2 * 256^3 = 2^25 cells each after the cap
+    two = md.md_workspace_size(cfg, md.make_replicas(sparse[:2]))
+    assert two < 53 * (1 << 26)  # 52 bytes per cell, and the rest of the plan
     with pytest.raises(md.KamdError) as e:
         md.md_workspace_size(cfg, md.make_replicas(sparse))
     assert e.value.code == md.KAMD_EINVAL and "cell grid" in str(e.value)
     adm, cnt = md.md_admit(cfg, md.make_replicas(sparse), 10 ** 12)
-    assert cnt == 8 and adm.tolist() == [1] * 8 + [0]
+    assert cnt == 2 and adm.tolist() == [1, 1, 0]
 
 
 def test_admission_by_footprint():
