@@ -107,12 +107,12 @@ struct Dev {
     const SegInfo *seg;
     const RepInfo *rep;
     const int32_t *wave_seg;
-    const int32_t *cell_seg;
     // cells and lists
     int32_t *cell_of, *rank, *cell_count, *cell_start, *cell_end, *order;
     int32_t *rb_force;    // per replica: rebuild at the next check regardless
-    int32_t *rb_any;      // [1]: number of waves that rebuild this step (set by the chain's gate kernel)
-    int32_t *rb_wlist;    // [nwaves]: those waves, replica by replica (set by the gate kernel)
+    int32_t *rb_any;      // [2]: number of waves, and of cells, that rebuild this step (gate kernel)
+    int32_t *rb_wlist;    // [nwaves]: those waves, replica by replica (gate kernel)
+    int32_t *rb_clist;    // [ncells]: those cells, replica by replica (gate kernel)
     uint32_t *maxdisp;    // per replica: max |r - r_build|^2 (float bits) since the last check
     int32_t *nbr;         // per wave: rows x 64 entries, see list_index
     int2 *kmax;           // per wave: entries of the A part, entries of the B part

@@ -15,18 +15,19 @@
 // that the decision stays on the device and the step loop can be captured in
 // a HIP graph:
 //   rb_gate       one block: rebuild flag of every replica (rebuild_flag),
-//                 worklist of the waves of the replicas that rebuild
+//                 worklists of the waves and of the cells of the replicas
+//                 that rebuild
 //   rb_assign     per listed wave: cell index and rank inside the cell of its
 //                 particles (one atomic per run of lanes that share a cell)
 //   rb_scan       per segment: exclusive scan of the counters -> cell ranges
 //   rb_scatter    per listed wave: provisional destination slot
-//   rb_sortgather per cell: order the cell by previous slot (a stable sort:
+//   rb_sortgather per listed cell: order the cell by previous slot (a stable sort:
 //                 the result does not depend on atomic timing), gather the
 //                 particles' state into the scratch arrays, clear the counter
 //   rb_list       per listed wave: copy its state back, record the build
 //                 position, write its neighbour list
-// Every kernel returns at once when the worklist is empty; the per-segment
-// and per-cell kernels also skip replicas whose flag is clear.
+// Every kernel returns at once when the worklists are empty; the
+// per-segment scan also skips replicas whose flag is clear.
 #include <climits>
 
 #include "common_dev.hpp"
@@ -34,65 +35,93 @@
 namespace kamd {
 
 // The gate: one block evaluates the rebuild flag of every replica and writes
-// the waves of the replicas that rebuild into the worklist rb_wlist (replica
-// by replica, in slot order), with their count in rb_any.  On the (most
-// frequent) steps without a rebuild every later kernel of the chain exits
-// after one load; on a step where a few replicas of a batch rebuild, the
-// per-wave kernels spread just those waves over the whole device.
+// two worklists: the waves of the replicas that rebuild (rb_wlist) and their
+// cells (rb_clist), replica by replica in slot order, with the counts in
+// rb_any[0] and rb_any[1].  On the (most frequent) steps without a rebuild
+// every later kernel of the chain exits after one load; on a step where a
+// few replicas of a batch rebuild, the per-wave and per-cell kernels spread
+// just their work over the whole device.
 constexpr int GATE_THREADS = 1024;
+
+// Append, for the replicas of one chunk (one per thread, n of them per
+// thread, numbered from first), the numbers first .. first + n - 1 to out,
+// in thread order.  Returns the number appended.  Every thread of the block
+// calls it.  The threads with n > 0 are compacted first; then the whole block
+// writes their ranges one after the other with plain stores.
+struct GateShared {
+    int wtot[GATE_THREADS / WAVE];  // per wavefront: sum of n, then its exclusive prefix
+    int wcnt[GATE_THREADS / WAVE];  // per wavefront: threads with n > 0, then their prefix
+    int tot, cnt;
+    int at[GATE_THREADS], first[GATE_THREADS], n[GATE_THREADS];  // compacted ranges
+};
+
+__device__ inline int gate_append(int32_t *out, int n, int first, GateShared &g)
+{
+    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+    int inc = n;  // inclusive scan over the wavefront
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        const int u = __shfl_up(inc, o, WAVE);
+        if (lane >= o) inc += u;
+    }
+    const uint64_t has = __ballot(n > 0);
+    const int rank = __popcll(has & ((1ull << lane) - 1ull));
+    if (lane == WAVE - 1) {
+        g.wtot[wv] = inc;
+        g.wcnt[wv] = __popcll(has);
+    }
+    __syncthreads();
+    if (t == 0) {
+        int run = 0, cnt = 0;
+        for (int k = 0; k < GATE_THREADS / WAVE; ++k) {
+            const int x = g.wtot[k], c = g.wcnt[k];
+            g.wtot[k] = run;
+            g.wcnt[k] = cnt;
+            run += x;
+            cnt += c;
+        }
+        g.tot = run;
+        g.cnt = cnt;
+    }
+    __syncthreads();
+    if (n > 0) {
+        const int k = g.wcnt[wv] + rank;
+        g.at[k] = g.wtot[wv] + inc - n;
+        g.first[k] = first;
+        g.n[k] = n;
+    }
+    __syncthreads();
+    const int cnt = g.cnt, tot = g.tot;
+    for (int k = 0; k < cnt; ++k)
+        for (int i = t; i < g.n[k]; i += GATE_THREADS) out[g.at[k] + i] = g.first[k] + i;
+    __syncthreads();  // the shared arrays are reused
+    return tot;
+}
 
 __global__ __launch_bounds__(GATE_THREADS) void k_rb_gate(Dev d)
 {
-    __shared__ int pre[GATE_THREADS + 1];  // exclusive prefix of the wave counts of one chunk of replicas
-    __shared__ int first[GATE_THREADS];    // first wave of each replica of the chunk
-    __shared__ int wtot[GATE_THREADS / WAVE];
-    const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
-    int base = 0;
+    __shared__ GateShared g;
+    int nwl = 0, ncl = 0;
     for (int r0 = 0; r0 < d.nrep; r0 += GATE_THREADS) {
-        const int r = r0 + t;
-        int nw = 0;
-        first[t] = 0;
+        const int r = r0 + threadIdx.x;
+        int nw = 0, w0 = 0, nc = 0, c0 = 0;
         if (r < d.nrep) {
-            first[t] = d.rep[r].wave0;
-            if (rebuild_flag(d, r)) nw = d.rep[r].wave1 - d.rep[r].wave0;
-        }
-        int inc = nw;  // inclusive scan over the wavefront, then over the wavefront totals
-#pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const int u = __shfl_up(inc, o, WAVE);
-            if (lane >= o) inc += u;
-        }
-        if (lane == WAVE - 1) wtot[wv] = inc;
-        __syncthreads();
-        if (t == 0) {
-            int run = 0;
-            for (int k = 0; k < GATE_THREADS / WAVE; ++k) {
-                const int x = wtot[k];
-                wtot[k] = run;
-                run += x;
+            const RepInfo &R = d.rep[r];
+            const SegInfo &SA = d.seg[R.seg[0]], &SB = d.seg[R.seg[1]];
+            w0 = R.wave0;
+            c0 = SA.cell0;  // the replica's two segments have consecutive cells
+            if (rebuild_flag(d, r)) {
+                nw = R.wave1 - R.wave0;
+                nc = SA.ncell + SB.ncell;
             }
-            pre[GATE_THREADS] = run;
         }
-        __syncthreads();
-        pre[t] = wtot[wv] + inc - nw;
-        __syncthreads();
-        const int tot = pre[GATE_THREADS];
-        // entry i belongs to the last replica k of the chunk with pre[k] <= i,
-        // which is one that rebuilds (a replica without waves shares its
-        // prefix with the next one)
-        for (int i = t; i < tot; i += GATE_THREADS) {
-            int lo = 0, hi = GATE_THREADS - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= i) lo = mid;
-                else hi = mid - 1;
-            }
-            d.rb_wlist[base + i] = first[lo] + (i - pre[lo]);
-        }
-        base += tot;
-        __syncthreads();  // the chunk's shared arrays are reused
+        nwl += gate_append(d.rb_wlist + nwl, nw, w0, g);
+        ncl += gate_append(d.rb_clist + ncl, nc, c0, g);
     }
-    if (t == 0) d.rb_any[0] = base;
+    if (threadIdx.x == 0) {
+        d.rb_any[0] = nwl;
+        d.rb_any[1] = ncl;
+    }
 }
 
 // Worklist entry of this wavefront for the per-wave kernels that run one
@@ -255,8 +284,6 @@ __device__ inline void gather_one(const Dev &d, int v, int t)
 // edge) fall back to a loop over memory.
 __device__ inline void sortgather_cell(const Dev &d, int c)
 {
-    const SegInfo &S = d.seg[d.cell_seg[c]];
-    if (!rebuild_flag(d, S.rep)) return;
     const int c0 = CELL_SUBX * c;
     const int st = d.cell_start[c0];
     const int m = d.cell_end[c0 + CELL_SUBX - 1] - st;
@@ -297,9 +324,11 @@ __device__ inline void sortgather_cell(const Dev &d, int c)
 
 __global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
 {
+    const int ncl = d.rb_any[1];  // cells of the replicas that rebuild
     if (d.rb_any[0] == 0) return;
     const int stride = gridDim.x * WAVES_PER_BLOCK;
-    for (int c = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); c < d.ncells; c += stride) sortgather_cell(d, c);
+    for (int i = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); i < ncl; i += stride)
+        sortgather_cell(d, d.rb_clist[i]);
 }
 
 // Neighbour lists.  One thread per particle.  Entries [0, kA) of a list hold

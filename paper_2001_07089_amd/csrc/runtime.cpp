@@ -27,14 +27,14 @@ struct kamd_ctx {
     std::vector<kamd_replica> reps;
     std::vector<SegInfo> segs;
     std::vector<RepInfo> rinfo;
-    std::vector<int32_t> wave_seg, cell_seg;
+    std::vector<int32_t> wave_seg;
     std::vector<int32_t> rdf_block_rep, rdf_block_start;
     kamd_state st{};
     hipStream_t stream = nullptr;
     int device = 0;
     Dev d{};
     std::vector<void *> allocs;       // everything owned
-    void *cells_alloc[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // count, start, end, seg
+    void *cells_alloc[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // count, start, end, cell worklist
     void *nbr_alloc = nullptr;
     int64_t rdf_cells_cap = 0;
     uint4 *mirror_alt = nullptr;      // second u32 mirror (fused force+drift steps)
@@ -125,7 +125,7 @@ static int validate(kamd_ctx *c, const kamd_config *cfg, const kamd_replica *rep
 struct Plan {
     std::vector<SegInfo> segs;
     std::vector<RepInfo> rinfo;
-    std::vector<int32_t> wave_seg, cell_seg;
+    std::vector<int32_t> wave_seg;
     int32_t npad = 0, nwaves = 0, ncells = 0, rows = 0, n_total = 0;
     int64_t ncells_wide = 0;  // the same count without 32-bit truncation
 };
@@ -156,7 +156,7 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
     auto cells_per_edge = [&](double box) {
         return (int)std::max(1.0, std::min(std::floor(box * reach / rlist), (double)cell_cap(dim_of(cfg))));
     };
-    for (int r = 0; r < n_rep; ++r) {  // the grid size first: an oversize plan builds no cell table
+    for (int r = 0; r < n_rep; ++r) {  // the grid size first (an oversize plan is refused)
         const int64_t nc = cells_per_edge(reps[r].box);
         P.ncells_wide += 2 * (planar ? nc * nc : nc * nc * nc);
     }
@@ -204,7 +204,6 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
             S.ncell = planar ? nc * nc : nc * nc * nc;
             R.seg[t] = (int32_t)P.segs.size();
             for (int w = 0; w < S.npad / WAVE; ++w) P.wave_seg.push_back(R.seg[t]);
-            if (fits) P.cell_seg.insert(P.cell_seg.end(), (size_t)S.ncell, R.seg[t]);
             slot += S.npad;
             cell += fits ? S.ncell : 0;
             P.segs.push_back(S);
@@ -340,7 +339,6 @@ static int upload_tables(kamd_ctx *c)
     HIPCHK(c, hipMemcpyAsync((void *)d.seg, c->segs.data(), sizeof(SegInfo) * c->segs.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync((void *)d.rep, c->rinfo.data(), sizeof(RepInfo) * c->rinfo.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync((void *)d.wave_seg, c->wave_seg.data(), 4 * c->wave_seg.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync((void *)d.cell_seg, c->cell_seg.data(), 4 * c->cell_seg.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return KAMD_OK;
 }
@@ -365,20 +363,20 @@ static int alloc_list_buffers(kamd_ctx *c, const Plan &P)
     }
     dfree(c, c->nbr_alloc);
     c->nbr_alloc = nullptr;
-    int32_t *cc, *cs, *ce, *csg;
+    int32_t *cc, *cs, *ce, *cl;
     const size_t nsub = (size_t)CELL_SUBX * P.ncells;  // counters and ranges per sub-cell
     TRY(dalloc(c, &cc, nsub));
     TRY(dalloc(c, &cs, nsub));
     TRY(dalloc(c, &ce, nsub));
-    TRY(dalloc(c, &csg, P.ncells));
+    TRY(dalloc(c, &cl, P.ncells));
     c->cells_alloc[0] = cc;
     c->cells_alloc[1] = cs;
     c->cells_alloc[2] = ce;
-    c->cells_alloc[3] = csg;
+    c->cells_alloc[3] = cl;
     d.cell_count = cc;
     d.cell_start = cs;
     d.cell_end = ce;
-    d.cell_seg = csg;
+    d.rb_clist = cl;
     int32_t *nb;
     TRY(dalloc(c, &nb, (size_t)P.rows * P.npad));
     c->nbr_alloc = nb;
@@ -423,7 +421,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     TRY(dalloc(c, &d.order, np));
     TRY(dalloc(c, &d.nlen, np));
     TRY(dalloc(c, &d.rb_force, d.nrep));
-    TRY(dalloc(c, &d.rb_any, 1));
+    TRY(dalloc(c, &d.rb_any, 2));
     TRY(dalloc(c, &d.rb_wlist, P.nwaves));
     TRY(dalloc(c, &c->md_base, 2 * (size_t)d.nrep));
     d.maxdisp = c->md_base;
@@ -447,7 +445,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     HIPCHK(c, launch_zero_i32((int32_t *)d.smirror, 4 * (np + LIST_UNROLL), c->stream));
     HIPCHK(c, launch_zero_i32(d.nlen, np, c->stream));
     HIPCHK(c, launch_zero_i32(d.rb_force, d.nrep, c->stream));
-    HIPCHK(c, launch_zero_i32(d.rb_any, 1, c->stream));
+    HIPCHK(c, launch_zero_i32(d.rb_any, 2, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)c->md_base, 2 * (int64_t)d.nrep, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)c->mirror_alt, 4 * np, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)d.kmax, 2 * (int64_t)P.nwaves, c->stream));
@@ -690,7 +688,6 @@ static int apply_list_params(kamd_ctx *c, double skin, int cell_div, bool first)
     c->segs = P.segs;
     c->rinfo = P.rinfo;
     c->wave_seg = P.wave_seg;
-    c->cell_seg = P.cell_seg;
     if (!first) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
         TRY(alloc_list_buffers(c, P));
