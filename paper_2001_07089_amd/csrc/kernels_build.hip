@@ -357,6 +357,22 @@ __global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
 // 2^32 range), converted to float; rl2_fx is enlarged by a few parts in 10^6
 // so that the list is a superset of the exact one.  The sorted mirror has
 // LIST_UNROLL spare entries past its end, so the unrolled loads need no clamp.
+// Maximum of v over the 64 lanes of a wavefront whose lanes are all active:
+// a running maximum along each row of 16 lanes by DPP row shifts (a lane
+// with no source lane in its row keeps the identity), then the last lane of
+// each row read into a scalar.  A few cycles, where a butterfly of lane
+// permutes waits on the LDS crossbar six times.
+__device__ inline int wave_max_all(int v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(v, 15), r1 = __builtin_amdgcn_readlane(v, 31);
+    const int r2 = __builtin_amdgcn_readlane(v, 47), r3 = __builtin_amdgcn_readlane(v, 63);
+    return max(max(r0, r1), max(r2, r3));
+}
+
 __device__ inline double gap(int o, int c, double cw, double u)
 {
     return o > 0 ? (c + o) * cw - u : (o < 0 ? u - (c + o + 1) * cw : 0.0);
@@ -369,8 +385,8 @@ __device__ inline double gap(int o, int c, double cw, double u)
 // store per candidate batch would expose the store latency on every batch.
 //
 // Candidate positions are staged too.  With one cell per list radius every
-// particle scans, per stencil row, at most three pieces: the wrapped high
-// end of the row, the main run of cells, the wrapped low end.  For each
+// particle scans, per stencil row, at most two pieces: the main run of cells
+// and, where the row wraps around the box, its wrapped end cell.  For each
 // piece the wavefront loads the union of its lanes' slot ranges into LDS
 // once, with coalesced loads, and the lanes then scan their own ranges out
 // of LDS; lanes of one cell read the same LDS words (a broadcast).  A union
@@ -434,7 +450,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     const int rows = d.rows;
     int row = 0;  // 32-bit words of the list used so far
     int total = 0;
-    int kpart[2], bpart[2];
+    int2 kpart = make_int2(0, 0), bpart = make_int2(-1, -1);  // per part: entries, base
     int n16 = 0;
     for (int tj = 0; tj < 2; ++tj) {
         const SegInfo &SJ = d.seg[R.seg[tj]];
@@ -459,8 +475,8 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                 lo = min(lo, cs(SJ.cell0 + (z0 * nc + y0) * nc));
                 hi = max(hi, ce(SJ.cell0 + (z1 * nc + y1) * nc + nc - 1));
             }
-            lo = -wave_max_i(-lo);
-            hi = wave_max_i(hi);
+            lo = -wave_max_all(-lo);
+            hi = wave_max_all(hi);
             if (hi - lo <= 65536) base = lo;
         }
         const bool half = base >= 0;
@@ -521,20 +537,40 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             }
             if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
         };
-        auto scan_staged = [&](int st, int en) __attribute__((always_inline)) {  // all lanes of the wavefront take part
+        // lowest start and highest end of the lanes' non-empty ranges
+        // (x = INT_MAX when no lane has one); all lanes take part
+        auto span = [&](int st, int en) __attribute__((always_inline)) {
             const bool has = st < en;
-            const int lo = -wave_max_i(has ? -st : INT_MIN + 1);
+            return make_int2(-wave_max_all(has ? -st : INT_MIN + 1), wave_max_all(has ? en : -1));
+        };
+        auto scan_staged = [&](int st, int en, int2 sp) __attribute__((always_inline)) {
+            const int lo = sp.x, hi = sp.y;
             if (lo == INT_MAX) return;
-            const int hi = wave_max_i(has ? en : -1);
             if (hi - lo > LIST_WIN) {
-                if (has) scan(st, en);
+                if (st < en) scan(st, en);
                 return;
             }
-            for (int e = lane; e < hi - lo; e += WAVE) {
-                const uint4 m = d.smirror[lo + e];
-                wx[e] = m.x;
-                wy[e] = m.y;
-                wz[e] = m.z;
+            // up to three loads per lane in flight at once, so that most
+            // unions take one memory round trip
+            const int n = hi - lo;
+            for (int e0 = 0; e0 < n; e0 += 3 * WAVE) {
+                uint4 m[3];
+#pragma unroll
+                for (int t = 0; t < 3; ++t)
+                    if (t == 0 || e0 + t * WAVE < n) m[t] = d.smirror[lo + min(e0 + t * WAVE + lane, n - 1)];
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    const int e = e0 + t * WAVE + lane;
+                    if (e < n) {
+                        wx[e] = m[t].x;
+                        wy[e] = m[t].y;
+                        wz[e] = m[t].z;
+                    }
+                }
+                // No load of this pass is left in flight.  Stated, so that the
+                // compiler need not wait for every load (the next row's bounds
+                // among them) before it reuses these registers.
+                __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -590,46 +626,64 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                 }
             }
         } else if (SJ.n > 0) {  // every lane walks the same rows: staged scans
-            for (int oz = oz0; oz < oz0 + nz; ++oz) {
-                const int qz = (cz + oz + nc) % nc;
-                for (int oy = -reach; oy < -reach + noff; ++oy) {
+            // Slot ranges of one stencil row: the main run of cells, and the
+            // end cell that wraps around the box where the row does.  Rows
+            // are read one step ahead of their scan, so that the loads of a
+            // row's bounds overlap the staging loads of the row before.
+            const int32_t *cstart = d.cell_start, *cend = d.cell_end;
+            const int cell0 = SJ.cell0;  // kept in a register across the list stores
+            auto bounds = [&](int oz, int oy) __attribute__((always_inline)) {
+                int4 b = make_int4(0, 0, 0, 0);
+                if (real) {
+                    const int qz = (cz + oz + nc) % nc;
                     const int qy = (cy + oy + nc) % nc;
-                    const int rowc = SJ.cell0 + (qz * nc + qy) * nc;  // cell (0, qy, qz)
-                    // pieces in list order: wrapped high end, main run, wrapped low end
-                    int s0 = 0, e0 = 0, s1 = 0, e1 = 0, s2 = 0, e2 = 0;
-                    if (real) {
-                        if (whole) {
-                            s1 = cs(rowc);
-                            e1 = ce(rowc + nc - 1);
-                        } else {
-                            // One cell per list radius (reach 1): a particle in
-                            // quarter qx of its cell is more than a cell edge,
-                            // and so more than the list radius, away along x
-                            // from the quarters of the left cell below qx and
-                            // of the right cell above qx; both are left out.
-                            const int a = cx - reach, b = cx + reach;
-                            const int32_t *cstart = d.cell_start, *cend = d.cell_end;
-                            if (a < 0) {  // the left cell wraps to the high end
-                                s0 = cstart[CELL_SUBX * (rowc + a + nc) + qx];
-                                e0 = cend[CELL_SUBX * (rowc + nc) - 1];
-                            }
-                            s1 = cstart[a < 0 ? CELL_SUBX * rowc : CELL_SUBX * (rowc + a) + qx];
-                            e1 = cend[b >= nc ? CELL_SUBX * (rowc + nc) - 1 : CELL_SUBX * (rowc + b) + qx];
-                            if (b >= nc) {  // the right cell wraps to the low end
-                                s2 = cstart[CELL_SUBX * rowc];
-                                e2 = cend[CELL_SUBX * (rowc + b - nc) + qx];
-                            }
+                    const int rowc = cell0 + (qz * nc + qy) * nc;  // cell (0, qy, qz)
+                    if (whole) {
+                        b.x = cs(rowc);
+                        b.y = ce(rowc + nc - 1);
+                    } else {
+                        // One cell per list radius (reach 1): a particle in
+                        // quarter qx of its cell is more than a cell edge, and
+                        // so more than the list radius, away along x from the
+                        // quarters of the left cell below qx and of the right
+                        // cell above qx; both are left out.
+                        const int a = cx - reach, e = cx + reach;
+                        b.x = cstart[a < 0 ? CELL_SUBX * rowc : CELL_SUBX * (rowc + a) + qx];
+                        b.y = cend[e >= nc ? CELL_SUBX * (rowc + nc) - 1 : CELL_SUBX * (rowc + e) + qx];
+                        // the left cell wraps to the high end of the row, or
+                        // the right cell to its low end
+                        const bool lw = a < 0;
+                        if (lw || e >= nc) {
+                            b.z = cstart[lw ? CELL_SUBX * (rowc + a + nc) + qx : CELL_SUBX * rowc];
+                            b.w = cend[lw ? CELL_SUBX * (rowc + nc) - 1 : CELL_SUBX * (rowc + e - nc) + qx];
                         }
                     }
-                    scan_staged(s0, e0);
-                    scan_staged(s1, e1);
-                    scan_staged(s2, e2);
                 }
+                return b;
+            };
+            const int nrow = nz * noff;
+            int oz = oz0, oy = -reach;
+            int4 next = bounds(oz, oy);
+            for (int r = 0; r < nrow; ++r) {
+                const int4 cur = next;
+                const int2 sp1 = span(cur.x, cur.y), sp2 = span(cur.z, cur.w);
+                // This row's bounds are used above, before the next row's
+                // loads are issued: a wait for them placed after those loads
+                // would wait for those loads too.
+                __builtin_amdgcn_sched_barrier(0);
+                // the next row; after the last one, row 0 again (read, not used)
+                if (++oy == -reach + noff) {
+                    oy = -reach;
+                    if (++oz == oz0 + nz) oz = oz0;
+                }
+                next = bounds(oz, oy);
+                scan_staged(cur.x, cur.y, sp1);
+                scan_staged(cur.z, cur.w, sp2);
             }
         }
         flush();
         total += cnt;
-        int kmax = wave_max_i(cnt);
+        int kmax = wave_max_all(cnt);
         const int align = half ? 2 * LIST_ROW_ALIGN : LIST_ROW_ALIGN;  // whole 16-byte words
         kmax = (kmax + align - 1) / align * align;
         if (done < cnt) {  // the last partial group, padded with the particle's own slot
@@ -647,20 +701,24 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         for (int k = row + (half ? done / 2 : done); k < row + words && k < rows; k += 4)
             *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = make_int4(pad, pad, pad, pad);
         if (row + words > rows && lane == 0) set_err(d.err, KAMD_DEV_LIST_OVERFLOW);
-        kpart[tj] = kmax;
-        bpart[tj] = base;
+        // selects rather than an array indexed by the part, which would
+        // live in scratch memory when this loop is not unrolled
+        kpart.x = tj == 0 ? kmax : kpart.x;
+        kpart.y = tj == 1 ? kmax : kpart.y;
+        bpart.x = tj == 0 ? base : bpart.x;
+        bpart.y = tj == 1 ? base : bpart.y;
         if (half) n16 = cnt - 1;  // 16-bit partner entries (the own slot is one of the cnt)
         row += words;
     }
     if (row > rows) {  // keep the force kernels inside the list
-        const int w0 = min(bpart[0] >= 0 ? kpart[0] / 2 : kpart[0], rows);
-        const int w1 = min(bpart[1] >= 0 ? kpart[1] / 2 : kpart[1], rows - w0);
-        kpart[0] = bpart[0] >= 0 ? 2 * w0 : w0;
-        kpart[1] = bpart[1] >= 0 ? 2 * w1 : w1;
+        const int w0 = min(bpart.x >= 0 ? kpart.x / 2 : kpart.x, rows);
+        const int w1 = min(bpart.y >= 0 ? kpart.y / 2 : kpart.y, rows - w0);
+        kpart.x = bpart.x >= 0 ? 2 * w0 : w0;
+        kpart.y = bpart.y >= 0 ? 2 * w1 : w1;
     }
     if (lane == 0) {
-        d.kmax[w] = make_int2(kpart[0], kpart[1]);
-        d.lbase[w] = make_int2(bpart[0], bpart[1]);
+        d.kmax[w] = kpart;
+        d.lbase[w] = bpart;
     }
     // partners (without the own slot) in the low 16 bits, those of them
     // stored as 16-bit entries in the high 16 bits
