@@ -373,6 +373,20 @@ __device__ inline int wave_max_all(int v)
     return max(max(r0, r1), max(r2, r3));
 }
 
+// Two signed 16-bit lanes of one 32-bit register.
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+// Squared separation in units of 2^16 fixed-point steps, from coordinates
+// reduced to their high 16 bits: x and y packed in one word (x low), z in the
+// low half of another.  Differences wrap modulo 2^16, which is the minimum
+// image, as for the full 32-bit coordinates; sums saturate.
+__device__ inline int r2_coarse(uint32_t ixy, uint32_t iz, uint32_t jxy, uint32_t jz)
+{
+    const short2_t dxy = __builtin_bit_cast(short2_t, ixy) - __builtin_bit_cast(short2_t, jxy);
+    const short2_t dz = __builtin_bit_cast(short2_t, iz) - __builtin_bit_cast(short2_t, jz);
+    return __builtin_amdgcn_sdot2(dz, dz, __builtin_amdgcn_sdot2(dxy, dxy, 0, true), true);
+}
+
 __device__ inline double gap(int o, int c, double cw, double u)
 {
     return o > 0 ? (c + o) * cw - u : (o < 0 ? u - (c + o + 1) * cw : 0.0);
@@ -393,6 +407,10 @@ __device__ inline double gap(int o, int c, double cw, double u)
 // longer than LIST_WIN (lanes in different rows of the grid) is scanned
 // straight from global memory instead.
 constexpr int LIST_STAGE = 16;
+// Boxes up to this edge (in the model's length unit) use the coarse staged
+// candidate test; a 2^16-step unit is then at most 0.0034, and the list grows
+// by under 0.6%.
+constexpr double COARSE_MAX_BOX = 220.0;
 constexpr int LIST_WIN = 384;
 
 __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
@@ -442,6 +460,11 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     const int oz0 = d.dim == 2 ? 0 : -reach, nz = d.dim == 2 ? 1 : noff;
     const double cw = 4294967296.0 / (double)nc;  // cell edge in fixed units
     const double ux = (double)mi.x, uy = (double)mi.y, uz = (double)mi.z;
+    // The staged candidate test compares coordinates reduced to their high
+    // 16 bits (x and y packed, z alone) when the box is small enough that the
+    // coarse units cost the list almost nothing (below); otherwise full ones.
+    const uint32_t ixy = (mi.x >> 16) | (mi.y & 0xffff0000u), iz = mi.z >> 16;
+    const bool coarse = R.L <= COARSE_MAX_BOX;
     int32_t *col = d.nbr + list_index(w, d.rows, 0, lane);
     int32_t(*buf)[WAVE] = stage[threadIdx.x / WAVE];
     uint32_t *wx = win_s[threadIdx.x / WAVE][0];
@@ -456,6 +479,14 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         const SegInfo &SJ = d.seg[R.seg[tj]];
         const float rl2 = R.rl2_fx[S.type + tj];
         const double rp = sqrt((double)rl2) + 4096.0;  // pruning radius with margin
+        // Coarse test.  Truncating both coordinates to 2^16-step units changes
+        // their difference by less than one unit per axis, so a pair within
+        // the list radius r (in those units) has a coarse separation below
+        // r + sqrt(3).  Accepting every coarse r2 below that bound squared
+        // keeps the list a superset of the exact one; the extra entries lie
+        // in a shell sqrt(3) units thick (0.3% more entries at L = 100).
+        const double rc16 = sqrt((double)rl2) * (1.0 / 65536.0) + 1.7320508075688772;
+        const int r2c = (int)ceil(rc16 * rc16) + 1;
         const double rp2 = rp * rp;
         // Entries of the part of the particle's own type are stored as 16-bit
         // offsets from a base slot, two to a 32-bit word, when every slot the
@@ -516,6 +547,11 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             buf[cnt & (LIST_STAGE - 1)][lane] = j;
             cnt += acc;
         };
+        auto test_coarse = [&](int j, bool in, uint32_t jxy, uint32_t jz) __attribute__((always_inline)) {
+            const int acc = (int)in & (int)(r2_coarse(ixy, iz, jxy, jz) < r2c);
+            buf[cnt & (LIST_STAGE - 1)][lane] = j;
+            cnt += acc;
+        };
         auto scan = [&](int st, int en) __attribute__((always_inline)) {  // straight from global memory
             int j = st;
             for (; j + LIST_UNROLL <= en; j += LIST_UNROLL) {  // whole batches
@@ -562,9 +598,14 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                 for (int t = 0; t < 3; ++t) {
                     const int e = e0 + t * WAVE + lane;
                     if (e < n) {
-                        wx[e] = m[t].x;
-                        wy[e] = m[t].y;
-                        wz[e] = m[t].z;
+                        if (coarse) {
+                            wx[e] = (m[t].x >> 16) | (m[t].y & 0xffff0000u);
+                            wy[e] = m[t].z >> 16;
+                        } else {
+                            wx[e] = m[t].x;
+                            wy[e] = m[t].y;
+                            wz[e] = m[t].z;
+                        }
                     }
                 }
                 // No load of this pass is left in flight.  Stated, so that the
@@ -575,16 +616,30 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
             int j = st;
-            for (; j + LIST_UNROLL <= en; j += LIST_UNROLL) {  // whole batches
-                const int o = j - lo;
+            if (coarse) {
+                for (; j + LIST_UNROLL <= en; j += LIST_UNROLL) {  // whole batches
+                    const int o = j - lo;
 #pragma unroll
-                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, true, wx[o + u], wy[o + u], wz[o + u]);
-                if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
-            }
-            if (j < en) {  // the last, partial batch
-                const int o = j - lo;
+                    for (int u = 0; u < LIST_UNROLL; ++u) test_coarse(j + u, true, wx[o + u], wy[o + u]);
+                    if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
+                }
+                if (j < en) {  // the last, partial batch
+                    const int o = j - lo;
 #pragma unroll
-                for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, j + u < en, wx[o + u], wy[o + u], wz[o + u]);
+                    for (int u = 0; u < LIST_UNROLL; ++u) test_coarse(j + u, j + u < en, wx[o + u], wy[o + u]);
+                }
+            } else {
+                for (; j + LIST_UNROLL <= en; j += LIST_UNROLL) {  // whole batches
+                    const int o = j - lo;
+#pragma unroll
+                    for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, true, wx[o + u], wy[o + u], wz[o + u]);
+                    if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
+                }
+                if (j < en) {  // the last, partial batch
+                    const int o = j - lo;
+#pragma unroll
+                    for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, j + u < en, wx[o + u], wy[o + u], wz[o + u]);
+                }
             }
             if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");

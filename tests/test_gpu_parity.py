@@ -670,3 +670,30 @@ def test_list_statistics_count_16bit_entries():
     assert 2.3 < ratio < 3.0
     assert st["max_list_len"] <= st["list_rows"]
     s.close()
+
+
+@pytest.mark.parametrize("n,rho", [(4000, 1.2), (3000, 0.02), (3000, 2.5e-4)])
+def test_list_holds_every_pair_within_the_list_radius(n, rho):
+    """Every ordered pair closer than its list radius r_c,ab + skin (Sec. III.C)
+    is in the Verlet list, and few others are.  The boxes of 14.9 and 53.1
+    use the list builder's candidate test on coordinates cut to 16 bits; the
+    box of 228.9 uses the full 32-bit test.  Exact pair counts: the oracle's
+    O(N^2) distance histogram with bin edges on the three list radii."""
+    skin, dr = 0.3, 0.1
+    L = W.box_for(n, rho)
+    na = W.n_a_for(n)
+    log(f"case list superset n={n} rho={rho} L={L:.1f}")
+    s = md.System([(n, na, L, 1.0, 41)], precision="mixed_fixed", init="rsa", min_dist=0.8, skin=skin)
+    s.forces()
+    assert s.status() == 0
+    a = s.numpy(("x", "y", "z"))
+    st = md.md_stats(s.ctx)
+    s.close()
+    h = O.rdf_hist(a["x"], a["y"], a["z"], na, L, dr, 30).astype(np.int64)
+    # hist rows AA, AB, BB: same-type pairs counted twice, AB pairs once
+    rl = [O.KA_RC_FACTOR * sg + skin for sg in O.KA_SIGMA]
+    k = [int(round(r / dr)) for r in rl]
+    exact = int(h[0, :k[0]].sum() + 2 * h[1, :k[1]].sum() + h[2, :k[2]].sum())
+    listed = int(round(st["mean_list_len"] * n))
+    log(f"  exact {exact} listed {listed}")
+    assert exact <= listed <= exact * 1.004 + 8
