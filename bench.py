@@ -26,8 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_PAIR = 19          # FP32 FLOPs per in-cutoff pair force (FMA = 2)
-# FP32 vector peak without packed-FP32 instructions (which this build does not
-# emit): 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz.  The published 157.3
+# FP32 vector peak without packed-FP32 instructions (the library is compiled
+# without them): 256 CUs x 64 lanes x 2 FLOP (FMA) x 2.4 GHz.  The published 157.3
 # TFLOP/s counts packed FP32 (two FMAs per lane per cycle).
 FP32_VECTOR_PEAK = 78.6     # TFLOP/s
 FP32_VECTOR_PEAK_PACKED = 157.3
@@ -356,7 +356,7 @@ def calibrate_copy(torch, mib):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py runs on exactly one GPU: this build has no multi-GPU path (asked for {a.gpus}).",
+        print(f"bench.py runs on exactly one GPU: the library has no multi-GPU path (asked for {a.gpus}).",
               file=sys.stderr)
         sys.exit(2)
     import torch

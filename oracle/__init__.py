@@ -10,10 +10,11 @@ Arrays are numpy float64 / int32 in the caller's particle order: the A block
 (indices 0..na-1) first, then the B block.  Image counters are int32 arrays of
 shape (3, n).
 
-Functions whose results are pinned by tests (closed forms, invariants, brute
-force, library routines) are listed in the design doc; the absolute energy level of
-a KA liquid and the RDF/MSD curve shapes are "parity unpinned" beyond the
-sanity bands given there.
+Each function is pinned by tests/test_oracle.py to something other than
+itself (closed forms, invariants, brute force, library routines); the absolute
+energy level of a KA liquid and the shapes of its RDF and MSD curves are
+"parity unpinned" (checked only for the excluded core and the uniform limit
+of g(r)).
 """
 import ctypes as C
 import math

@@ -7,8 +7,7 @@ from.
 
 Workload shapes follow the paper's Kob-Andersen mixture (Sec. II.B: 80:20,
 number density about 1.2, N = 1000 with L = 9.4 in the paper's examples) and
-the scaled-up single-system and replica-batch configurations described in
-the design doc.  The paper's own configuration files are not available, so every
+the scaled-up single-system and replica-batch configurations defined below.  The paper's own configuration files are not available, so every
 configuration is generated here from a seed.
 """
 from dataclasses import dataclass, field

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped cleanly where no GPU is visible (they are run on
-    # the GPU machine with -m gpu).
+    # an MI355X with -m gpu).
     try:
         import torch
         has_gpu = torch.cuda.is_available()

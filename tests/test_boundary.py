@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(md.EXPORTED)
 
 
-def test_header_has_north_star_entry_points():
+def test_header_declares_the_hot_path_entry_points():
     names = _declared()
     for n in ("md_init", "md_build_cells", "md_forces", "md_step_nve", "md_step_nvt", "md_rdf", "md_msd"):
         assert n in names

@@ -2,7 +2,7 @@
 
 Inputs are seeded synthetic Kob-Andersen liquids (jittered lattice relaxed by
 the oracle's own stochastic-bath run) fed identically to both sides.
-Tolerances (DESIGN.md): forces normwise 1e-12 (FP64) / 1e-5 (mixed);
+Tolerances: forces normwise 1e-12 (FP64) / 1e-5 (mixed);
 RDF counts bit-exact; MSD and thermostat draws 1e-12; short trajectories
 within the rounding growth of a few tens of steps.
 """
