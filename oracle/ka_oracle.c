@@ -356,6 +356,9 @@ void ora_gauss3(uint64_t seed, uint32_t rep, uint32_t tag, uint32_t id, double g
  * scaling (m = 1, nothing to do); (3) subtract the centre-of-mass velocity;
  * (4) rescale so that sum v^2 = d N T exactly (Eq. (equip3N), with 3
  * replaced by d for the planar system of the appendix, which keeps vz = 0).
+ * A single particle has no velocity left after step (3); step (4) then has
+ * nothing to rescale and the particle stays at rest (the flow chart does not
+ * treat n = 1; this is the reading taken).
  * ids[i] is the counter word identifying particle i (its index in the
  * caller's order); NULL means ids[i] = i.  dim is 3 or 2. */
 void ora_mb_velocities_d(int dim, int n, double T, uint64_t seed, uint32_t rep, uint32_t tag,
@@ -375,7 +378,7 @@ void ora_mb_velocities_d(int dim, int n, double T, uint64_t seed, uint32_t rep, 
     for (int i = 0; i < n; ++i) { vx[i] -= sx; vy[i] -= sy; vz[i] -= sz; }
     double s2 = 0.0;
     for (int i = 0; i < n; ++i) s2 += vx[i] * vx[i] + vy[i] * vy[i] + vz[i] * vz[i];
-    double scale = sqrt((double)dim * T * (double)n / s2);
+    double scale = s2 > 0.0 ? sqrt((double)dim * T * (double)n / s2) : 0.0;
     for (int i = 0; i < n; ++i) { vx[i] *= scale; vy[i] *= scale; vz[i] *= scale; }
 }
 

@@ -270,14 +270,16 @@ __global__ __launch_bounds__(BLOCK) void k_mb_center(Dev d)
     if (lane_id() == 0) d.wred[4 * c.w + 0] = k2;
 }
 
-// Step 4: rescale so that sum v^2 = 3 N T (Eq. (equip3N)).
+// Step 4: rescale so that sum v^2 = 3 N T (Eq. (equip3N)).  A replica of one
+// particle has no velocity left after step 3 and stays at rest.
 __global__ __launch_bounds__(BLOCK) void k_mb_scale(Dev d)
 {
     SlotCtx c;
     if (!slot_ctx(d, c)) return;
     if (!c.real) return;
     const RepInfo &R = d.rep[c.rep];
-    const double f = sqrt((double)d.dim * R.T * (double)R.n / d.rsum[4 * c.rep + 0]);
+    const double s2 = d.rsum[4 * c.rep + 0];
+    const double f = s2 > 0.0 ? sqrt((double)d.dim * R.T * (double)R.n / s2) : 0.0;
     d.vx[c.s] *= f;
     d.vy[c.s] *= f;
     d.vz[c.s] *= f;

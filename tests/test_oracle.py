@@ -318,6 +318,18 @@ def test_mb_flow_chart_invariants():
     assert np.max(np.abs(wx - vx)) > 0.1
 
 
+def test_mb_draw_of_one_and_two_particles():
+    """Two particles: after the centre-of-mass step their velocities are equal
+    and opposite, and the rescale still gives sum v^2 = 3 N T.  One particle:
+    nothing is left after that step, and it stays at rest (no 0/0)."""
+    vx, vy, vz = O.mb_velocities(2, 0.7, seed=5, rep=0, tag=1)
+    for v in (vx, vy, vz):
+        assert v[0] == pytest.approx(-v[1], rel=1e-14, abs=1e-15)
+    assert (vx @ vx + vy @ vy + vz @ vz) == pytest.approx(3 * 2 * 0.7, rel=1e-13)
+    vx, vy, vz = O.mb_velocities(1, 0.7, seed=5, rep=0, tag=1)
+    assert vx.tolist() == [0.0] and vy.tolist() == [0.0] and vz.tolist() == [0.0]
+
+
 def test_stochastic_bath_resets_temperature():
     st = _liquid(n=500, T=1.5, seed=16)
     e = O.run(st, 0.005, 50, nb=10, T=0.2, seed=3)
