@@ -115,6 +115,8 @@ __global__ __launch_bounds__(GATE_THREADS) void k_rb_gate(Dev d)
                 nc = SA.ncell + SB.ncell;
             }
         }
+        // most steps rebuild nothing: skip the compaction (block-uniform)
+        if (!__syncthreads_or(nw > 0)) continue;
         nwl += gate_append(d.rb_wlist + nwl, nw, w0, g);
         ncl += gate_append(d.rb_clist + ncl, nc, c0, g);
     }
