@@ -99,6 +99,7 @@ struct Dev {
     int32_t *id;          // caller global index or -1
     uint4 *mirror;        // u32 fixed-point positions (x, y, z, 0)
     uint4 *mbuild;        // mirror at the last list build
+    double4 *pos4;        // FP64 positions (x, y, z, 0) packed for the FP64 force kernel's gathers
     // permutation scratch (same layout)
     double *sx, *sy, *sz, *svx, *svy, *svz, *sax, *say, *saz;
     int32_t *simg, *sid;

@@ -247,6 +247,7 @@ static size_t plan_bytes(const Plan &P, int n_rep)
     size_t b = 0;
     b += 2 * (9 * 8 + 3 * 4 + 4 + 16) * np;  // state + scratch
     b += 16 * np + 16 * LIST_UNROLL;           // mbuild, tail of the sorted mirror
+    b += 32 * np;                              // packed FP64 positions
     b += 4 * np * 3;                           // cell_of, rank, order
     b += 4 * np;                               // nlen
     b += 4 * (size_t)P.ncells_wide * 3 * CELL_SUBX;  // count/start/end per sub-cell
@@ -406,6 +407,7 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     TRY(dalloc(c, &d.sid, np));
     TRY(dalloc(c, &d.mirror, np));
     TRY(dalloc(c, &d.mbuild, np));
+    TRY(dalloc(c, &d.pos4, np));
     TRY(dalloc(c, &d.smirror, np + LIST_UNROLL));  // the list scan reads up to 7 past a range
     SegInfo *sg;
     RepInfo *ri;
