@@ -13,7 +13,8 @@
 namespace kamd {
 
 // RDF grid: per replica rdf_nc^3 cells (a planar system: one layer of
-// rdf_nc^2) of edge L/rdf_nc >= n_bins*dr, both particle types together.
+// rdf_nc^2) of edge L/rdf_nc >= n_bins*dr, or >= n_bins*dr/2 where such cells
+// still hold several particles; both particle types together.
 // Counting sort into rdf_pos (replica-relative positions, w = type + 2*cell).
 __global__ __launch_bounds__(BLOCK) void k_rdf_assign(Dev d)
 {
@@ -79,9 +80,20 @@ __device__ inline double min_image_branch(double dd, double L, double half)
 }
 
 // One block of BLOCK particles of one replica (block table from the host).
-// Each particle visits the distinct stencil cells of its own and counts the
-// partners with a larger index, so every unordered pair is counted once.
+// Each particle visits the distinct cells of its stencil (3 per axis with
+// cells as wide as the histogram range r_max, 5 with cells half as wide) that
+// come within r_max of it, and counts the partners with a larger index there,
+// so every unordered pair is counted once: a partner within range lies in a
+// cell within range of both particles, and the one with the smaller index
+// counts it.  With the finer cells, leaving out the far ones takes the
+// candidates per particle from 27 cells of edge r_max to about 10 of them.
 // Block-local u32 histograms in LDS, flushed to the uint64 result.
+__device__ inline double cell_gap(int o, int c, double cw, double u)
+{
+    // distance along one axis from coordinate u (in cell c) to cell c + o
+    return o > 0 ? (c + o) * cw - u : (o < 0 ? u - (c + o + 1) * cw : 0.0);
+}
+
 __global__ __launch_bounds__(BLOCK) void k_rdf_hist(Dev d, double dr, int nbins, uint64_t *hist)
 {
     extern __shared__ uint32_t lh[];  // [3][nbins]
@@ -99,15 +111,30 @@ __global__ __launch_bounds__(BLOCK) void k_rdf_hist(Dev d, double dr, int nbins,
         const int cl = wi >> 1;
         const int nc = R.rdf_nc;
         const int cx = cl % nc, cy = (cl / nc) % nc, cz = cl / (nc * nc);
-        const int noff = min(nc, 3);
-        const int oz0 = d.dim == 2 ? 0 : -1, nz = d.dim == 2 ? 1 : noff;  // planar: one layer
-        const double L = R.L, half = 0.5 * R.L;
+        const double L = R.L;
+        const double rmax = nbins * dr;
+        const int reach = rmax * nc > L * (1.0 + 1e-12) ? 2 : 1;  // cells narrower than r_max
+        const int noff = min(nc, 2 * reach + 1);
+        const bool whole = nc < 2 * reach + 1;  // every cell along an axis is in the stencil
+        const int oz0 = d.dim == 2 ? 0 : -reach, nz = d.dim == 2 ? 1 : noff;  // planar: one layer
+        const double half = 0.5 * R.L;
+        const double cw = L / nc;
+        // pruning radius: the histogram range with a margin far above rounding
+        const double rp = rmax * (1.0 + 1e-9) + 1e-12 * L;
+        const double rp2 = rp * rp;
         for (int oz = oz0; oz < oz0 + nz; ++oz) {
-            const int qz = (cz + oz + nc) % nc;
-            for (int oy = -1; oy < -1 + noff; ++oy) {
-                const int qy = (cy + oy + nc) % nc;
-                for (int ox = -1; ox < -1 + noff; ++ox) {
-                    const int qx = (cx + ox + nc) % nc;
+            const double gz = whole ? 0.0 : cell_gap(oz, cz, cw, pi.z);
+            if (gz * gz > rp2) continue;
+            const int qz = (cz + oz + 2 * nc) % nc;
+            for (int oy = -reach; oy < -reach + noff; ++oy) {
+                const double gy = whole ? 0.0 : cell_gap(oy, cy, cw, pi.y);
+                const double g2 = gy * gy + gz * gz;
+                if (g2 > rp2) continue;
+                const int qy = (cy + oy + 2 * nc) % nc;
+                for (int ox = -reach; ox < -reach + noff; ++ox) {
+                    const double gx = whole ? 0.0 : cell_gap(ox, cx, cw, pi.x);
+                    if (gx * gx + g2 > rp2) continue;
+                    const int qx = (cx + ox + 2 * nc) % nc;
                     const int c = R.rdf_cell0 + (qz * nc + qy) * nc + qx;
                     const int st = d.rdf_start[c];
                     const int en = st + d.rdf_count[c];

@@ -889,7 +889,13 @@ extern "C" int md_rdf(kamd_ctx *c, double dr, int32_t n_bins, uint64_t *hist_dev
         const double L = c->reps[r].box;
         if (rmax > 0.5 * L * (1.0 + 1e-12)) return fail(c, KAMD_EINVAL, "n_bins*dr = %.9g exceeds L/2 = %.9g (replica %zu)", rmax, 0.5 * L, r);
         const bool planar = dim_of(&c->cfg) == 2;
-        const int nc = (int)std::max(1.0, std::min(std::floor(L / rmax), (double)cell_cap(dim_of(&c->cfg))));
+        // Cells as wide as the histogram range (a 3-cell stencil per axis), or
+        // half as wide (5 cells, the far ones skipped per particle) where they
+        // still hold several particles: fewer candidates, but more cells.
+        const int dim = dim_of(&c->cfg);
+        const double half_range_cell = c->reps[r].n / std::pow(L, dim) * std::pow(0.5 * rmax, dim);
+        const double per_range = half_range_cell >= 6.0 ? 2.0 : 1.0;
+        const int nc = (int)std::max(1.0, std::min(std::floor(per_range * L / rmax), (double)cell_cap(dim)));
         const int ncell = planar ? nc * nc : nc * nc * nc;
         c->rinfo[r].rdf_nc = nc;
         c->rinfo[r].rdf_cell0 = (int32_t)std::min<int64_t>(cells, INT32_MAX);

@@ -169,8 +169,11 @@ def test_nve_fp64_trajectory_matches_oracle():
     s.close()
 
 
-@pytest.mark.parametrize("n,dr_mode", [(1000, "paper"), (4000, "halfbox200"), (3000, "short")])
+@pytest.mark.parametrize("n,dr_mode", [(1000, "paper"), (4000, "halfbox200"), (3000, "short"), (6000, "pruned")])
 def test_rdf_counts_bit_exact(n, dr_mode):
+    """Histogram counts equal the oracle's O(N^2) ones.  "pruned": r_max = 4.0
+    in a box of 17.1, where the grid takes cells of half the range (8 per
+    edge) and each particle skips the stencil cells beyond r_max."""
     log(f"case rdf n={n} {dr_mode}")
     rho = 1.2
     if dr_mode == "paper":  # N = 1000, L = 9.4, dr = 0.1, n_bins = int(L/2/dr) (Sec. VI.A.1)
@@ -182,6 +185,8 @@ def test_rdf_counts_bit_exact(n, dr_mode):
         dr, nb = (L / 2) / 200, 200
     elif dr_mode == "short":
         dr, nb = 0.02, 150
+    elif dr_mode == "pruned":
+        dr, nb = 0.1, 40
     s = system([(n, 1.0, 12, rho)], "fp64")
     h = s._host(s.rdf(dr, nb)).astype(np.uint64)[0]
     ref = O.rdf_hist(x, y, z, na, L, dr, nb)
