@@ -99,7 +99,7 @@ struct Dev {
     int32_t *id;          // caller global index or -1
     uint4 *mirror;        // u32 fixed-point positions (x, y, z, 0)
     uint4 *mbuild;        // mirror at the last list build
-    double4 *pos4;        // FP64 positions (x, y, z, 0) packed for the FP64 force kernel's gathers
+    double4 *pos4;        // FP64 only (else null): positions (x, y, z, 0) packed for the force kernel's gathers
     // permutation scratch (same layout)
     double *sx, *sy, *sz, *svx, *svy, *svz, *sax, *say, *saz;
     int32_t *simg, *sid;
@@ -156,10 +156,14 @@ hipError_t launch_rb_list(const Dev &d, int cell_div, hipStream_t s);
 // The force kernel also closes the step's rebuild check (resets maxdisp and
 // rb_force) and, with step_inc, advances the device step counter.
 hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, bool step_inc, hipStream_t s);
-// Mixed precisions, NVE: forces fused with the closing half kick and the next
-// drift (new mirror into mirror_out, displacement maximum into md_out).
+// NVE: forces fused with the closing half kick and the next drift (new
+// mirror into mirror_out, displacement maximum into md_out; FP64 also the
+// packed positions into pos4_out, which must differ from d.pos4 and is
+// ignored by the mixed precisions).
 hipError_t launch_force_kd(const Dev &d, const Model &m, int prec, double dt, uint4 *mirror_out, uint32_t *md_out,
-                           hipStream_t s);
+                           double4 *pos4_out, hipStream_t s);
+// Pack d.x, d.y, d.z into d.pos4 (every slot, padding included).
+hipError_t launch_pack_pos(const Dev &d, hipStream_t s);
 
 hipError_t launch_drift(const Dev &d, double dt, hipStream_t s);
 hipError_t launch_drift_nh(const Dev &d, double dt, hipStream_t s);

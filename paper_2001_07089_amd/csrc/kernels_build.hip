@@ -448,6 +448,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         d.mirror[s] = mi;
         d.mbuild[s] = mi;
     }
+    if (d.pos4) d.pos4[s] = make_double4(d.x[s], d.y[s], d.z[s], 0.0);  // FP64: gathers see the new order
     const int nc = R.nc;
     const int noff = min(nc, 2 * reach + 1);
     const bool whole = nc < 2 * reach + 1;  // every cell of a row is in the stencil

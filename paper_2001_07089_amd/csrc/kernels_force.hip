@@ -85,13 +85,25 @@ __global__ __launch_bounds__(BLOCK) void k_pack_pos(Dev d)
     if (s < d.npad_total) d.pos4[s] = make_double4(d.x[s], d.y[s], d.z[s], 0.0);
 }
 
-template <bool ENERGY>
-__global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_inc)
+// KD (NVE steps only): as in the mixed kernel below, the force of slot s
+// closes the step's half kick and opens the next one (drift, wrap, new
+// mirror into mirror_out, displacement into md_out).  Neighbours gather from
+// d.pos4, so the new positions go to d.x, d.y, d.z in place and, packed, to
+// pos4_out (a different buffer), where the next step's neighbours find them.
+// Padding slots copy their unchanged position, which keeps their own list
+// entry at zero separation.
+template <bool ENERGY, bool KD>
+__global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_inc, double dt, uint4 *mirror_out,
+                                                       uint32_t *md_out, double4 *pos4_out)
 {
     close_step(d, step_inc);
     const int w = wave_id_remapped();
-    if (w >= d.nwaves) return;
+    const bool valid = w < d.nwaves;
+    float d2 = 0.0f;
+    int rep = -1;
+    if (valid) {
     const SegInfo &S = d.seg[d.wave_seg[w]];
+    rep = S.rep;
     const RepInfo &R = d.rep[S.rep];
     const int s = w * WAVE + lane_id();
     const double L = R.L, invL = R.invL;
@@ -163,10 +175,20 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
         }
         row += base >= 0 ? nrows / 2 : nrows;
     }
-    d.ax[s] = fx;
-    d.ay[s] = fy;
-    d.az[s] = fz;
     if (!(isfinite(fx) && isfinite(fy) && isfinite(fz))) set_err(d.err, KAMD_DEV_NONFINITE);
+    if (!KD) {
+        d.ax[s] = fx;
+        d.ay[s] = fy;
+        d.az[s] = fz;
+    } else if ((s - S.slot0) < S.n) {
+        const double h = 0.5 * dt;
+        const double a[3] = {fx, fy, fz};
+        const double v[3] = {fma(h, fx, d.vx[s]), fma(h, fy, d.vy[s]), fma(h, fz, d.vz[s])};
+        drift_core(d, s, R, dt, 0.0, 0.0, h, v, a, mirror_out, d2);
+        pos4_out[s] = make_double4(d.x[s], d.y[s], d.z[s], 0.0);
+    } else {
+        pos4_out[s] = make_double4(xi, yi, zi, 0.0);
+    }
     if (ENERGY) {
         pe = wave_sum(pe);
         vir = wave_sum(vir);
@@ -177,6 +199,8 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
             d.wred[4 * w + 3] = npair;
         }
     }
+    }
+    if (KD) block_disp_max(md_out, valid, rep, d2);
 }
 
 // KD (NVE steps only): after the force of slot s, close the step with the
@@ -319,8 +343,12 @@ hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, boo
     const int si = step_inc ? 1 : 0;
     if (prec == 0) {
         hipLaunchKernelGGL(k_pack_pos, dim3((d.npad_total + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, d);
-        if (energy) hipLaunchKernelGGL(k_force_fp64<true>, dim3(nb), dim3(BLOCK), 0, s, d, m, si);
-        else hipLaunchKernelGGL(k_force_fp64<false>, dim3(nb), dim3(BLOCK), 0, s, d, m, si);
+        if (energy)
+            hipLaunchKernelGGL((k_force_fp64<true, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
+                               (uint4 *)nullptr, (uint32_t *)nullptr, (double4 *)nullptr);
+        else
+            hipLaunchKernelGGL((k_force_fp64<false, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
+                               (uint4 *)nullptr, (uint32_t *)nullptr, (double4 *)nullptr);
     } else if (prec == 1) {
         if (energy)
             hipLaunchKernelGGL((k_force_mixed<false, true, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
@@ -339,11 +367,21 @@ hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, boo
     return hipGetLastError();
 }
 
+hipError_t launch_pack_pos(const Dev &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_pos, dim3((d.npad_total + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, d);
+    return hipGetLastError();
+}
+
 hipError_t launch_force_kd(const Dev &d, const Model &m, int prec, double dt, uint4 *mirror_out, uint32_t *md_out,
-                           hipStream_t s)
+                           double4 *pos4_out, hipStream_t s)
 {
     const int nb = (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-    if (prec == 1)
+    if (prec == 0) {
+        if (!d.pos4 || !pos4_out || pos4_out == d.pos4) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_force_fp64<false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out, md_out,
+                           pos4_out);
+    } else if (prec == 1)
         hipLaunchKernelGGL((k_force_mixed<false, false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out,
                            md_out);
     else if (prec == 2)

@@ -38,6 +38,7 @@ struct kamd_ctx {
     void *nbr_alloc = nullptr;
     int64_t rdf_cells_cap = 0;
     uint4 *mirror_alt = nullptr;      // second u32 mirror (fused force+drift steps)
+    double4 *pos4_alt = nullptr;      // second packed FP64 position buffer (FP64 fused steps)
     uint32_t *md_base = nullptr;      // [2][n_rep] displacement maxima
     double *Q_dev = nullptr;
     double *rep_arg = nullptr;        // per-replica host arguments staged for a kernel
@@ -128,6 +129,7 @@ struct Plan {
     std::vector<int32_t> wave_seg;
     int32_t npad = 0, nwaves = 0, ncells = 0, rows = 0, n_total = 0;
     int64_t ncells_wide = 0;  // the same count without 32-bit truncation
+    bool fp64 = false;        // FP64 precision: two packed position buffers
 };
 
 // Limits of the list cell grid.  A segment holds at most 2^24 cells (nc is
@@ -152,6 +154,7 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
     const double rlist = rcmax + skin;
     const double cap = cfg->list_capacity > 0.0 ? cfg->list_capacity : 1.6;
     P = Plan();
+    P.fp64 = cfg->precision == KAMD_PREC_FP64;
     const bool planar = dim_of(cfg) == 2;
     auto cells_per_edge = [&](double box) {
         return (int)std::max(1.0, std::min(std::floor(box * reach / rlist), (double)cell_cap(dim_of(cfg))));
@@ -247,7 +250,7 @@ static size_t plan_bytes(const Plan &P, int n_rep)
     size_t b = 0;
     b += 2 * (9 * 8 + 3 * 4 + 4 + 16) * np;  // state + scratch
     b += 16 * np + 16 * LIST_UNROLL;           // mbuild, tail of the sorted mirror
-    b += 32 * np;                              // packed FP64 positions
+    b += (P.fp64 ? 64 : 0) * np;               // packed FP64 positions, two buffers
     b += 4 * np * 3;                           // cell_of, rank, order
     b += 4 * np;                               // nlen
     b += 4 * (size_t)P.ncells_wide * 3 * CELL_SUBX;  // count/start/end per sub-cell
@@ -407,7 +410,12 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     TRY(dalloc(c, &d.sid, np));
     TRY(dalloc(c, &d.mirror, np));
     TRY(dalloc(c, &d.mbuild, np));
-    TRY(dalloc(c, &d.pos4, np));
+    d.pos4 = nullptr;
+    c->pos4_alt = nullptr;
+    if (c->cfg.precision == KAMD_PREC_FP64) {
+        TRY(dalloc(c, &d.pos4, np));
+        TRY(dalloc(c, &c->pos4_alt, np));
+    }
     TRY(dalloc(c, &d.smirror, np + LIST_UNROLL));  // the list scan reads up to 7 past a range
     SegInfo *sg;
     RepInfo *ri;
@@ -615,41 +623,49 @@ static int enqueue_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb
         return KAMD_OK;
     }
     const bool stoch = ensemble == 1 && mode == KAMD_NVT_STOCHASTIC;
-    // Mixed precisions fuse the force of a step with its closing half kick
-    // and the next drift whenever no thermostat acts in between.  Fused steps
-    // alternate the two position mirrors and the two displacement buffers;
-    // their number is made even so that every call starts and ends on the
-    // first buffers (which keeps graph replays consistent).
+    // The force of a step is fused with its closing half kick and the next
+    // drift whenever no thermostat acts in between.  Fused steps alternate
+    // the two position mirrors, the two displacement buffers and (FP64) the
+    // two packed position buffers; their number is made even so that every
+    // call starts and ends on the first buffers (which keeps graph replays
+    // consistent).
     std::vector<char> fused(nsteps + 1, 0);
     int nf = 0;
     for (int s = 1; s < nsteps; ++s) {
         const int64_t gstep = c->step + s;
         const bool reassign = stoch && nb > 0 && (gstep % nb) == 0;
-        fused[s] = (prec != KAMD_PREC_FP64) && !reassign;
+        fused[s] = !reassign;
         nf += fused[s];
     }
     if (nf % 2)
         for (int s = 1; s < nsteps; ++s)
             if (fused[s]) { fused[s] = 0; break; }
     uint4 *mir[2] = {c->d.mirror, c->mirror_alt};
+    double4 *p4[2] = {c->d.pos4, c->pos4_alt};
     int cur = 0, par = 0;
     Dev dd = c->d;
-    bool need_drift = true;
+    bool need_drift = true, p4_ok = false;
     for (int s = 1; s <= nsteps; ++s) {
         dd.mirror = mir[cur];
         dd.maxdisp = c->md_base + par * c->d.nrep;
+        dd.pos4 = p4[cur];
         if (need_drift) HIPCHK(c, launch_drift(dd, dt, c->stream));
         TRY(rebuild_chain(c, dd));
         const int64_t gstep = c->step + s;
         const bool reassign = stoch && nb > 0 && (gstep % nb) == 0;
         if (fused[s]) {
+            // the packed positions are current after a fused FP64 step (the
+            // list build reorders them with the rest); otherwise pack them
+            if (prec == KAMD_PREC_FP64 && !p4_ok) HIPCHK(c, launch_pack_pos(dd, c->stream));
             HIPCHK(c, launch_force_kd(dd, c->model, prec, dt, mir[1 - cur], c->md_base + (1 - par) * c->d.nrep,
-                                      c->stream));
+                                      p4[1 - cur], c->stream));
             cur = 1 - cur;
             par = 1 - par;
             need_drift = false;
+            p4_ok = true;
             continue;
         }
+        p4_ok = false;
         HIPCHK(c, launch_force(dd, c->model, prec, false, true, c->stream));
         if (s == nsteps || reassign) {
             HIPCHK(c, launch_kick_nve(dd, dt, false, c->stream));
@@ -1287,7 +1303,7 @@ extern "C" int md_profile(kamd_ctx *c, int32_t nsteps, double *host_out)
     std::vector<char> fused(nsteps + 1, 0);
     int nf = 0;
     for (int s = 1; s < nsteps; ++s) {
-        fused[s] = prec != KAMD_PREC_FP64;
+        fused[s] = 1;
         nf += fused[s];
     }
     if (nf % 2)
@@ -1299,26 +1315,31 @@ extern "C" int md_profile(kamd_ctx *c, int32_t nsteps, double *host_out)
     HIPCHK(c, hipMemcpyAsync(cnt0, c->d.counters, 32, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     uint4 *mir[2] = {c->d.mirror, c->mirror_alt};
+    double4 *p4[2] = {c->d.pos4, c->pos4_alt};
     int cur = 0, par = 0;
     Dev dd = c->d;
-    bool need_drift = true;
+    bool need_drift = true, p4_ok = false;
     size_t k = 0;
     HIPCHK(c, hipEventRecord(ev[k++], c->stream));
     for (int s = 1; s <= nsteps; ++s) {
         dd.mirror = mir[cur];
         dd.maxdisp = c->md_base + par * c->d.nrep;
+        dd.pos4 = p4[cur];
         HIPCHK(c, hipEventRecord(ev[k++], c->stream));
         if (need_drift) HIPCHK(c, launch_drift(dd, dt, c->stream));
         HIPCHK(c, hipEventRecord(ev[k++], c->stream));
         TRY(rebuild_chain(c, dd));
         HIPCHK(c, hipEventRecord(ev[k++], c->stream));
         if (fused[s]) {
+            if (prec == KAMD_PREC_FP64 && !p4_ok) HIPCHK(c, launch_pack_pos(dd, c->stream));
             HIPCHK(c, launch_force_kd(dd, c->model, prec, dt, mir[1 - cur], c->md_base + (1 - par) * c->d.nrep,
-                                      c->stream));
+                                      p4[1 - cur], c->stream));
             cur = 1 - cur;
             par = 1 - par;
             need_drift = false;
+            p4_ok = true;
         } else {
+            p4_ok = false;
             HIPCHK(c, launch_force(dd, c->model, prec, false, true, c->stream));
         }
         HIPCHK(c, hipEventRecord(ev[k++], c->stream));

@@ -287,6 +287,54 @@ def test_graph_replay_stochastic_bath():
     s2.close()
 
 
+def test_fp64_fused_steps_through_rebuilds_and_redraws():
+    """FP64 steps fuse the force with the closing half kick and the next drift,
+    except the last step of a call and a step followed by a redraw.  A hot
+    liquid (T = 2.0) over 80 steps with a redraw every 9 steps crosses many
+    list rebuilds, which reorder the packed positions the fused steps gather,
+    and alternates fused and unfused steps; the trajectory follows the
+    oracle's stochastic-bath run."""
+    n, T, seed = 1500, 2.0, 26
+    log("case fp64 fused steps")
+    s = system([(n, T, seed, 1.2)], "fp64")
+    x, y, z, vx, vy, vz, na, L = relaxed(n, T, seed)
+    st = O.State(x, y, z, vx, vy, vz, na, L)
+    st.compute_forces()
+    nsteps, nb = 80, 9
+    O.run(st, 0.005, nsteps, nb=nb, T=T, seed=1000 + seed, rep=0)
+    r0 = md.md_stats(s.ctx)["rebuilds"]
+    s.step_nvt(nsteps, md.NVT_STOCHASTIC, n_reassign=nb)
+    assert md.md_stats(s.ctx)["rebuilds"] - r0 >= 3
+    a = s.numpy()
+    img = s.images()
+    assert np.array_equal(img, st.img)
+    for k, o in (("x", st.x), ("y", st.y), ("z", st.z)):
+        assert np.max(np.abs(a[k] - o)) < 1e-8, k
+    for k, o in (("vx", st.vx), ("vy", st.vy), ("vz", st.vz)):
+        assert np.max(np.abs(a[k] - o)) < 1e-8, k
+    assert s.status() == 0
+    s.close()
+
+
+def test_graph_replay_equals_eager_fp64():
+    """Graph replays of fused FP64 steps: each replay packs the positions
+    afresh at its first fused step, so replays and eager calls agree bit for
+    bit."""
+    log("case graph replay fp64")
+    cfg = [(2000, 1.5, 27, 1.2)]
+    s1 = system(cfg, "fp64")
+    s2 = system(cfg, "fp64")
+    md.md_graph_capture(s2.ctx, 40, 0)
+    for _ in range(3):
+        s1.step_nve(40)
+        md.md_graph_launch(s2.ctx)
+        s2.sync()
+        assert _state_equal(s1.numpy(), s2.numpy())
+    assert s1.status() == 0 and s2.status() == 0
+    s1.close()
+    s2.close()
+
+
 def test_replica_in_batch_equals_alone_fixed():
     log("case batch invariance")
     a_cfg = (2000, 0.9, 18, 1.2)
