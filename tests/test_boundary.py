@@ -38,6 +38,21 @@ def _reps(ns, rho=1.2, T=1.0):
     return md.make_replicas([(n, W.n_a_for(n), W.box_for(n, rho), T, 7 + i) for i, n in enumerate(ns)])
 
 
+def test_workspace_holds_packed_positions_for_fp64_only():
+    """FP64 contexts keep two packed (x, y, z, 0) position buffers of 32 B per
+    padded slot for the fused steps; the mixed precisions gather the u32
+    mirror and keep none.  Every type segment is padded to 64 slots."""
+    ns = [1000, 333, 4097]
+    npad = 0
+    for n in ns:
+        na = W.n_a_for(n)
+        npad += -(-na // 64) * 64 + -(-(n - na) // 64) * 64
+    f = md.md_workspace_size(md.make_config("fp64"), _reps(ns))
+    for prec in ("mixed", "mixed_fixed"):
+        m = md.md_workspace_size(md.make_config(prec), _reps(ns))
+        assert f - m == 64 * npad, prec
+
+
 def test_workspace_size_scales_with_particles():
     cfg = md.make_config()
     a = md.md_workspace_size(cfg, _reps([1000]))
