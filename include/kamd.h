@@ -77,7 +77,9 @@ enum {
 enum {
     KAMD_DEV_NONFINITE = 1u,     /* a position, velocity or force became inf/nan       */
     KAMD_DEV_LIST_OVERFLOW = 2u, /* a neighbour list exceeded its capacity            */
-    KAMD_DEV_FORCE_RANGE = 4u    /* a pair force left the fixed-point range            */
+    KAMD_DEV_FORCE_RANGE = 4u    /* MIXED_FIXED: a pair came so close that its force
+                                    reached 2^25 (beyond it the 2^-26-unit rounding is
+                                    no longer exact), or a net force exceeded 1e8     */
 };
 
 /* Pair model: epsilon and sigma per pair type in the order AA, AB, BB, and the
@@ -135,6 +137,13 @@ typedef struct {
                                energy LAMMPS pair style lj/cut reports (Sec. IV.B).
                                Forces are the same either way; only PE, E_tot and
                                everything derived from them change               */
+    int32_t sample_every;   /* > 0: record the observables of every replica at the
+                               end of every step whose number is a multiple of
+                               this (after any thermostat action of that step)
+                               into a device ring buffer read by md_observables;
+                               0: no sampling.  Works inside captured graphs     */
+    int32_t sample_capacity;/* rows of the ring buffer per replica (0 = 1024); the
+                               oldest rows are overwritten                        */
 } kamd_config;
 
 /* Device bytes md_init would allocate for this configuration (host call, no
@@ -240,11 +249,26 @@ int md_scale_velocities(kamd_ctx *ctx, const double *factor);
  * count to *count.  KAMD_EINVAL for n_md < 1, t0 < 0.5, kmax < 1. */
 int md_log_schedule(int32_t n_md, double t0, int32_t kmax, int32_t *out, int32_t max_out, int32_t *count);
 
-/* Current observables per replica into host_out (host, FP64 [n_rep][6]):
- * {KE, PE, W, T, E_tot, P} with KE = sum v^2/2, PE the shifted potential,
- * T = 2 KE / (3N) (Eq. (equip3N)), E_tot = KE + PE (Eq. (EsysNpart)) and
- * pressure P = N T / V + W / (3V).  Syncs. */
-int md_observables(kamd_ctx *ctx, double *host_out);
+/* Sampled observables (the quantities the paper follows along a run: kinetic,
+ * potential and total energy, Sec. III.F and Eq. (EsysNpart); temperature,
+ * Eq. (equip3N)).  Rows written on the device every cfg.sample_every steps
+ * (eager steps and graph replays alike).  host_out (host, FP64
+ * [n_rep][max_rows][6]) receives, per replica, the most recent
+ * rows = min(max_rows, rows held) samples in chronological order, each
+ * {step, KE, PE, E_tot, T, W}: KE = sum v^2/2, PE the potential energy (shifted
+ * unless pe_unshifted), E_tot = KE + PE, T = 2 KE / (d N), W the virial.
+ * *rows receives the count (0 when sampling is off).  Syncs. */
+int md_observables(kamd_ctx *ctx, double *host_out, int32_t max_rows, int32_t *rows);
+
+/* Forget every sampled row (the next sample starts the ring again). */
+int md_clear_samples(kamd_ctx *ctx);
+
+/* Observables of the current state per replica into host_out (host, FP64
+ * [n_rep][6]): {KE, PE, W, T, E_tot, P} with KE = sum v^2/2, PE the shifted
+ * potential, T = 2 KE / (3N) (Eq. (equip3N)), E_tot = KE + PE (Eq.
+ * (EsysNpart)) and pressure P = N T / V + W / (3V).  Runs one energy pass of
+ * the force kernel.  Syncs. */
+int md_observables_now(kamd_ctx *ctx, double *host_out);
 
 /* Nose-Hoover state per replica into host_out (host, FP64 [n_rep][2]):
  * {xi, ln s}.  Syncs. */

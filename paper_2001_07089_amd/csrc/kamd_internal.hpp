@@ -67,7 +67,8 @@ struct RepInfo {
     float rc2_fx[3];       // r_c(ab)^2 / h^2
     float rl2_fx[3];       // (r_c(ab) + skin)^2 / h^2, slightly enlarged
     float sig2_fx[3];      // sigma(ab)^2 / h^2
-    float pad0_;
+    float ir2_lim_fx[3];   // h^2 / r_lim(ab)^2: a pair closer than r_lim has a force whose
+                           // 2^-26-unit rounding in MIXED_FIXED is no longer exact
     double c48_h[3];       // 48 eps(ab) / h: converts the fixed-unit sum to a force
     double fix_k[3];       // 48 eps(ab) / h * FIX_SCALE
     double fx_to_len;      // h
@@ -133,6 +134,10 @@ struct Dev {
     const int32_t *rdf_block_start;
     // MSD origins [16][3][n_total] in caller order
     double *origin;
+    // sampled observables [nrep][ring_cap][6]: step, KE, PE, E_tot, T, W
+    // (null when sampling is off); counters[2] counts the rows written
+    double *ring;
+    int32_t ring_cap;
     // sizes
     int32_t npad_total;
     int32_t n_total;
@@ -160,8 +165,10 @@ hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, boo
 // mirror into mirror_out, displacement maximum into md_out; FP64 also the
 // packed positions into pos4_out, which must differ from d.pos4 and is
 // ignored by the mixed precisions).
+// With energy, also the per-wave partials wred[0..3] = {sum v(t)^2, PE, W,
+// pairs} of the step's end state (v(t) is the closed half kick).
 hipError_t launch_force_kd(const Dev &d, const Model &m, int prec, double dt, uint4 *mirror_out, uint32_t *md_out,
-                           double4 *pos4_out, hipStream_t s);
+                           double4 *pos4_out, bool energy, hipStream_t s);
 // Pack d.x, d.y, d.z into d.pos4 (every slot, padding included).
 hipError_t launch_pack_pos(const Dev &d, hipStream_t s);
 
@@ -189,6 +196,9 @@ hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_store_obs(const Dev &d, double *out, hipStream_t s);
 hipError_t launch_store_pe_w(const Dev &d, double *out, hipStream_t s);
+// One row of the observables ring from rsum: mask 1 KE, 2 PE and W, 4 step,
+// E_tot and T, then advance the row counter (counters[2]).
+hipError_t launch_sample(const Dev &d, int mask, hipStream_t s);
 
 hipError_t launch_rdf_prepare(const Dev &d, hipStream_t s);
 hipError_t launch_rdf(const Dev &d, double dr, int nbins, int nblocks, uint64_t *hist, hipStream_t s);

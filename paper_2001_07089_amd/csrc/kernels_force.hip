@@ -26,7 +26,10 @@
 //   2  MIXED_FIXED: as MIXED, but every pair force component is rounded to an
 //      integer number of 2^-26 force units (one FP64 fma against 1.5*2^52)
 //      and summed in 64-bit integers, so the sum is exact and independent of
-//      the order of the list; F_ij = -F_ji holds bit for bit.
+//      the order of the list; F_ij = -F_ji holds bit for bit.  The rounding
+//      is exact only while |F| < 2^25 per pair: each list part tracks its
+//      largest in-cutoff 1/r^2 and the kernel sets KAMD_DEV_FORCE_RANGE when
+//      a pair came closer than the separation where that bound is reached.
 #include "common_dev.hpp"
 
 namespace kamd {
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
     const double xi = d.x[s], yi = d.y[s], zi = d.z[s];
     const int2 km = d.kmax[w];
     const int2 lb = d.lbase[w];
-    double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, vir = 0.0, npair = 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, vir = 0.0, npair = 0.0, ke2 = 0.0;
     int row = 0;  // 32-bit words of the list
 #pragma unroll 1
     for (int tj = 0; tj < 2; ++tj) {
@@ -184,6 +187,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
         const double h = 0.5 * dt;
         const double a[3] = {fx, fy, fz};
         const double v[3] = {fma(h, fx, d.vx[s]), fma(h, fy, d.vy[s]), fma(h, fz, d.vz[s])};
+        if (ENERGY) ke2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         drift_core(d, s, R, dt, 0.0, 0.0, h, v, a, mirror_out, d2);
         pos4_out[s] = make_double4(d.x[s], d.y[s], d.z[s], 0.0);
     } else {
@@ -193,7 +197,9 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
         pe = wave_sum(pe);
         vir = wave_sum(vir);
         npair = wave_sum(npair);
+        if (KD) ke2 = wave_sum(ke2);
         if (lane_id() == 0) {
+            if (KD) d.wred[4 * w + 0] = ke2;
             d.wred[4 * w + 1] = pe;
             d.wred[4 * w + 2] = vir;
             d.wred[4 * w + 3] = npair;
@@ -225,8 +231,9 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
     const uint4 mi = d.mirror[s];
     const int2 km = d.kmax[w];
     const int2 lb = d.lbase[w];
-    double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, vir = 0.0, npair = 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, vir = 0.0, npair = 0.0, ke2 = 0.0;
     uint64_t qx = 0, qy = 0, qz = 0;
+    bool range_bad = false;
     int row = 0;  // 32-bit words of the list
 #pragma unroll 1
     for (int tj = 0; tj < 2; ++tj) {
@@ -236,6 +243,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
         const int nrows = tj ? km.y : km.x;
         const int base = tj ? lb.y : lb.x;
         float sx = 0.0f, sy = 0.0f, sz = 0.0f, se = 0.0f, sv = 0.0f;
+        float irmax = 0.0f;  // largest 1/r^2 of an in-cutoff pair (fixed-point range check)
         int cnt = 0;
         const int4 *nb = reinterpret_cast<const int4 *>(d.nbr + list_index(w, d.rows, row, lane_id()));
         auto pair = [&](const uint4 mj) {
@@ -251,6 +259,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
                 const float t = s6 * (s6 - 0.5f);
                 const float f = t * ir2;
                 if (FIXED) {
+                    irmax = fmaxf(irmax, ir2);
                     const double wd = (double)f * fk;
                     qx += (uint64_t)__double_as_longlong(fma(wd, (double)ix, FIX_MAGIC));
                     qy += (uint64_t)__double_as_longlong(fma(wd, (double)iy, FIX_MAGIC));
@@ -287,6 +296,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
             }
         }
         if (FIXED) {
+            range_bad = range_bad || irmax > R.ir2_lim_fx[p];
             const uint64_t mb = (uint64_t)__double_as_longlong(FIX_MAGIC) * (uint64_t)nrows;
             qx -= mb;
             qy -= mb;
@@ -309,8 +319,10 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
         fx = (double)(int64_t)qx * inv;
         fy = (double)(int64_t)qy * inv;
         fz = (double)(int64_t)qz * inv;
+        // the per-pair bound, and a net force beyond which the int64 -> FP64
+        // conversion of the sum is no longer exact (2^53 units)
         const double lim = 1.0e8;
-        if (fabs(fx) > lim || fabs(fy) > lim || fabs(fz) > lim) set_err(d.err, KAMD_DEV_FORCE_RANGE);
+        if (range_bad || fabs(fx) > lim || fabs(fy) > lim || fabs(fz) > lim) set_err(d.err, KAMD_DEV_FORCE_RANGE);
     }
     if (!(isfinite(fx) && isfinite(fy) && isfinite(fz))) set_err(d.err, KAMD_DEV_NONFINITE);
     if (!KD) {
@@ -321,13 +333,16 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
         const double h = 0.5 * dt;
         const double a[3] = {fx, fy, fz};
         const double v[3] = {fma(h, fx, d.vx[s]), fma(h, fy, d.vy[s]), fma(h, fz, d.vz[s])};
+        if (ENERGY) ke2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         drift_core(d, s, R, dt, 0.0, 0.0, h, v, a, mirror_out, d2);
     }
     if (ENERGY) {
         pe = wave_sum(pe);
         vir = wave_sum(vir);
         npair = wave_sum(npair);
+        if (KD) ke2 = wave_sum(ke2);
         if (lane_id() == 0) {
+            if (KD) d.wred[4 * w + 0] = ke2;
             d.wred[4 * w + 1] = pe;
             d.wred[4 * w + 2] = vir;
             d.wred[4 * w + 3] = npair;
@@ -374,21 +389,34 @@ hipError_t launch_pack_pos(const Dev &d, hipStream_t s)
 }
 
 hipError_t launch_force_kd(const Dev &d, const Model &m, int prec, double dt, uint4 *mirror_out, uint32_t *md_out,
-                           double4 *pos4_out, hipStream_t s)
+                           double4 *pos4_out, bool energy, hipStream_t s)
 {
     const int nb = (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
     if (prec == 0) {
         if (!d.pos4 || !pos4_out || pos4_out == d.pos4) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_force_fp64<false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out, md_out,
-                           pos4_out);
-    } else if (prec == 1)
-        hipLaunchKernelGGL((k_force_mixed<false, false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out,
-                           md_out);
-    else if (prec == 2)
-        hipLaunchKernelGGL((k_force_mixed<true, false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out,
-                           md_out);
-    else
+        if (energy)
+            hipLaunchKernelGGL((k_force_fp64<true, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out,
+                               md_out, pos4_out);
+        else
+            hipLaunchKernelGGL((k_force_fp64<false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out,
+                               md_out, pos4_out);
+    } else if (prec == 1) {
+        if (energy)
+            hipLaunchKernelGGL((k_force_mixed<false, true, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt,
+                               mirror_out, md_out);
+        else
+            hipLaunchKernelGGL((k_force_mixed<false, false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt,
+                               mirror_out, md_out);
+    } else if (prec == 2) {
+        if (energy)
+            hipLaunchKernelGGL((k_force_mixed<true, true, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt,
+                               mirror_out, md_out);
+        else
+            hipLaunchKernelGGL((k_force_mixed<true, false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt,
+                               mirror_out, md_out);
+    } else {
         return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -388,6 +388,32 @@ __global__ void k_store_pe_w(Dev d, double *out)
     out[2 * r + 1] = d.rsum[4 * r + 2];
 }
 
+// One row of the observables ring per replica, from the per-replica sums in
+// rsum (Eq. (EsysNpart): E_tot = KE + PE; Eq. (equip3N): T = 2 KE / (d N)).
+// A row may be filled in two launches (PE and W before a velocity redraw, KE
+// after it); mask 4 completes it and advances the row counter.  One block.
+__global__ __launch_bounds__(BLOCK) void k_sample(Dev d, int mask)
+{
+    const int idx = d.counters[2];
+    const int slot = idx % d.ring_cap;
+    for (int r = threadIdx.x; r < d.nrep; r += BLOCK) {
+        double *row = d.ring + ((size_t)r * d.ring_cap + slot) * 6;
+        const double *rs = d.rsum + 4 * r;
+        if (mask & 1) row[1] = 0.5 * rs[0];
+        if (mask & 2) {
+            row[2] = rs[1];
+            row[5] = rs[2];
+        }
+        if (mask & 4) {
+            row[0] = (double)d.counters[1];
+            row[3] = row[1] + row[2];
+            row[4] = 2.0 * row[1] / ((double)d.dim * (double)d.rep[r].n);
+        }
+    }
+    __syncthreads();
+    if ((mask & 4) && threadIdx.x == 0) d.counters[2] = idx + 1;
+}
+
 // ------------------------------------------------------------- launchers
 static inline int nblk(const Dev &d) { return (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
 
@@ -503,6 +529,12 @@ hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s)
 hipError_t launch_store_pe_w(const Dev &d, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_store_pe_w, dim3((d.nrep + 63) / 64), dim3(64), 0, s, d, out);
+    return hipGetLastError();
+}
+hipError_t launch_sample(const Dev &d, int mask, hipStream_t s)
+{
+    if (!d.ring || d.ring_cap <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample, dim3(1), dim3(BLOCK), 0, s, d, mask);
     return hipGetLastError();
 }
 hipError_t launch_store_obs(const Dev &d, double *out, hipStream_t s)

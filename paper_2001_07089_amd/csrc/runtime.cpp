@@ -92,6 +92,32 @@ static void model_from(const kamd_model &m, Model &out, double &rc_max)
     }
 }
 
+// Smallest separation at which the pair force of one pair type can still be
+// rounded exactly to 2^-26 force units by the MIXED_FIXED kernels: the
+// rounding adds the scaled component to 1.5 * 2^52, which is exact while
+// |F| 2^26 < 2^51, i.e. |F| < 2^25.  The pair force magnitude
+// 48 |eps| s6 |s6 - 1/2| / r (s6 = (sigma/r)^6, Eq. (KAFix)) falls
+// monotonically on (0, 2^(1/6) sigma), so bisection finds where it crosses
+// 2^25 (less a 2^-8 margin for the FP32 pair arithmetic).  0 when the model
+// has no such crossing (eps = 0).
+static double fixed_range_rmin(double eps, double sigma)
+{
+    const double flim = std::ldexp(1.0, 25) * (1.0 - std::ldexp(1.0, -8));
+    auto F = [&](double r) {
+        const double sr2 = (sigma / r) * (sigma / r);
+        const double s6 = sr2 * sr2 * sr2;
+        return 48.0 * std::fabs(eps) * s6 * std::fabs(s6 - 0.5) / r;
+    };
+    double lo = 1e-6 * sigma, hi = std::pow(2.0, 1.0 / 6.0) * sigma;
+    if (!(F(lo) > flim)) return 0.0;
+    for (int k = 0; k < 200; ++k) {
+        const double mid = 0.5 * (lo + hi);
+        if (F(mid) > flim) lo = mid;
+        else hi = mid;
+    }
+    return hi;
+}
+
 static inline int dim_of(const kamd_config *cfg) { return cfg->dim == 2 ? 2 : 3; }
 
 static int validate(kamd_ctx *c, const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep)
@@ -102,6 +128,8 @@ static int validate(kamd_ctx *c, const kamd_config *cfg, const kamd_replica *rep
     if (cfg->cell_div < 0 || cfg->cell_div > 2) return fail(c, KAMD_EINVAL, "cell_div must be 0, 1 or 2");
     if (cfg->dim != 0 && cfg->dim != 2 && cfg->dim != 3) return fail(c, KAMD_EINVAL, "dim must be 0, 2 or 3");
     if (cfg->pe_unshifted != 0 && cfg->pe_unshifted != 1) return fail(c, KAMD_EINVAL, "pe_unshifted must be 0 or 1");
+    if (cfg->sample_every < 0 || cfg->sample_capacity < 0 || cfg->sample_capacity > (1 << 24))
+        return fail(c, KAMD_EINVAL, "sample_every must be >= 0 and sample_capacity in [0, 2^24]");
     if (!(cfg->model.rc_factor > 0.0)) return fail(c, KAMD_EINVAL, "rc_factor must be > 0");
     for (int p = 0; p < 3; ++p)
         if (!(cfg->model.sigma[p] > 0.0) || !std::isfinite(cfg->model.eps[p]))
@@ -143,6 +171,13 @@ constexpr int64_t MAX_PLAN_CELLS = (int64_t)1 << 26;
 static int cell_cap(int dim) { return dim == 2 ? 4096 : 256; }  // nc^(dim) <= MAX_SEG_CELLS
 
 static double list_skin(const kamd_config *cfg) { return cfg->skin < 0.0 ? 0.3 : cfg->skin; }
+
+// Rows per replica of the observables ring (0 when sampling is off).
+static int ring_rows(const kamd_config *cfg)
+{
+    if (cfg->sample_every <= 0) return 0;
+    return cfg->sample_capacity > 0 ? cfg->sample_capacity : 1024;
+}
 
 static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_rep, double skin, int cell_div,
                       Plan &P)
@@ -191,6 +226,10 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
             R.sig2_fx[p] = (float)((cfg->model.sigma[p] / h) * (cfg->model.sigma[p] / h));
             R.c48_h[p] = 48.0 * cfg->model.eps[p] / h;
             R.fix_k[p] = R.c48_h[p] * FIX_SCALE;
+            // a pair is flagged when its 1/r^2 (fixed units) exceeds this; the
+            // 1e-5 margin covers the rounding of the device's FP32 reciprocal
+            const double rmin = fixed_range_rmin(cfg->model.eps[p], cfg->model.sigma[p]);
+            R.ir2_lim_fx[p] = rmin > 0.0 ? (float)((h / rmin) * (h / rmin) * (1.0 - 1e-5)) : INFINITY;
         }
         R.fx_to_len = h;
         R.wave0 = slot / WAVE;
@@ -447,6 +486,9 @@ static int alloc_all(kamd_ctx *c, const Plan &P)
     TRY(dalloc(c, &c->Q_dev, d.nrep));
     TRY(dalloc(c, &c->rep_arg, d.nrep));
     TRY(dalloc(c, &c->obs_stage, 4 * (size_t)d.nrep));
+    d.ring_cap = ring_rows(&c->cfg);
+    d.ring = nullptr;
+    if (d.ring_cap > 0) TRY(dalloc(c, &d.ring, 6 * (size_t)d.nrep * d.ring_cap));
     // zero everything that is read before written
     for (auto p : f64) HIPCHK(c, launch_zero_f64(*p, np, c->stream));
     HIPCHK(c, launch_zero_i32(d.img, 3 * np, c->stream));
@@ -599,6 +641,12 @@ static int do_export(kamd_ctx *c)
 
 static int maybe_export(kamd_ctx *c) { return c->cfg.auto_sync ? do_export(c) : KAMD_OK; }
 
+// Whether the observables are sampled at the end of global step gstep.
+static bool sample_step(const kamd_ctx *c, int64_t gstep)
+{
+    return c->d.ring && c->cfg.sample_every > 0 && gstep % c->cfg.sample_every == 0;
+}
+
 // Enqueue nsteps steps.  ensemble 0: NVE; 1: NVT with mode/nb/tau.
 // device_tags: the Maxwell-Boltzmann draw tags come from the device step
 // counter (graph replays), else from the host counter.
@@ -612,13 +660,15 @@ static int enqueue_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb
         HIPCHK(c, launch_rep_reduce(d, 1, c->stream));
         HIPCHK(c, launch_set_k2(d, c->stream));
         for (int s = 1; s <= nsteps; ++s) {
+            const bool smp = sample_step(c, c->step + s);
             HIPCHK(c, launch_nh_begin(d, dt, c->Q_dev, c->stream));
             HIPCHK(c, launch_drift_nh(d, dt, c->stream));
             TRY(rebuild_chain(c, c->d));
-            HIPCHK(c, launch_force(d, c->model, prec, false, true, c->stream));
+            HIPCHK(c, launch_force(d, c->model, prec, smp, true, c->stream));
             HIPCHK(c, launch_kick_nh(d, c->stream));
-            HIPCHK(c, launch_rep_reduce(d, 1, c->stream));
+            HIPCHK(c, launch_rep_reduce(d, smp ? 7 : 1, c->stream));
             HIPCHK(c, launch_nh_end(d, dt, c->Q_dev, c->stream));
+            if (smp) HIPCHK(c, launch_sample(d, 7, c->stream));
         }
         return KAMD_OK;
     }
@@ -653,12 +703,17 @@ static int enqueue_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb
         TRY(rebuild_chain(c, dd));
         const int64_t gstep = c->step + s;
         const bool reassign = stoch && nb > 0 && (gstep % nb) == 0;
+        const bool smp = sample_step(c, gstep);
         if (fused[s]) {
             // the packed positions are current after a fused FP64 step (the
             // list build reorders them with the rest); otherwise pack them
             if (prec == KAMD_PREC_FP64 && !p4_ok) HIPCHK(c, launch_pack_pos(dd, c->stream));
             HIPCHK(c, launch_force_kd(dd, c->model, prec, dt, mir[1 - cur], c->md_base + (1 - par) * c->d.nrep,
-                                      p4[1 - cur], c->stream));
+                                      p4[1 - cur], smp, c->stream));
+            if (smp) {
+                HIPCHK(c, launch_rep_reduce(dd, 7, c->stream));
+                HIPCHK(c, launch_sample(dd, 7, c->stream));
+            }
             cur = 1 - cur;
             par = 1 - par;
             need_drift = false;
@@ -666,13 +721,33 @@ static int enqueue_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb
             continue;
         }
         p4_ok = false;
-        HIPCHK(c, launch_force(dd, c->model, prec, false, true, c->stream));
+        HIPCHK(c, launch_force(dd, c->model, prec, smp, true, c->stream));
         if (s == nsteps || reassign) {
-            HIPCHK(c, launch_kick_nve(dd, dt, false, c->stream));
-            if (reassign) TRY(mb_reassign(c, device_tags, (uint32_t)gstep));
+            HIPCHK(c, launch_kick_nve(dd, dt, smp, c->stream));
+            if (reassign) {
+                // a sample describes the end of the step: PE and W now, KE
+                // after the redraw
+                if (smp) {
+                    HIPCHK(c, launch_rep_reduce(dd, 6, c->stream));
+                    HIPCHK(c, launch_sample(dd, 2, c->stream));
+                }
+                TRY(mb_reassign(c, device_tags, (uint32_t)gstep));
+                if (smp) {
+                    HIPCHK(c, launch_ke_partial(dd, c->stream));
+                    HIPCHK(c, launch_rep_reduce(dd, 1, c->stream));
+                    HIPCHK(c, launch_sample(dd, 5, c->stream));
+                }
+            } else if (smp) {
+                HIPCHK(c, launch_rep_reduce(dd, 7, c->stream));
+                HIPCHK(c, launch_sample(dd, 7, c->stream));
+            }
             need_drift = true;
         } else {
-            HIPCHK(c, launch_kick_drift(dd, dt, false, c->stream));
+            HIPCHK(c, launch_kick_drift(dd, dt, smp, c->stream));
+            if (smp) {
+                HIPCHK(c, launch_rep_reduce(dd, 7, c->stream));
+                HIPCHK(c, launch_sample(dd, 7, c->stream));
+            }
             need_drift = false;
         }
     }
@@ -972,7 +1047,37 @@ extern "C" int md_van_hove(kamd_ctx *c, int32_t slot, double dr, int32_t n_bins,
     return KAMD_OK;
 }
 
-extern "C" int md_observables(kamd_ctx *c, double *host_out)
+extern "C" int md_observables(kamd_ctx *c, double *host_out, int32_t max_rows, int32_t *rows)
+{
+    if (!c || !rows || max_rows < 0 || (max_rows > 0 && !host_out)) return fail(c, KAMD_EINVAL, "bad arguments");
+    *rows = 0;
+    const Dev &d = c->d;
+    if (!d.ring) return KAMD_OK;
+    const size_t nr = c->reps.size(), cap = (size_t)d.ring_cap;
+    int32_t cnt[8];
+    std::vector<double> ring(6 * nr * cap);
+    HIPCHK(c, hipMemcpyAsync(cnt, d.counters, 32, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ring.data(), d.ring, 8 * ring.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int64_t total = cnt[2];
+    const int64_t k = std::min<int64_t>(std::min<int64_t>(total, (int64_t)cap), max_rows);
+    for (size_t r = 0; r < nr; ++r)
+        for (int64_t i = 0; i < k; ++i) {
+            const size_t slot = (size_t)((total - k + i) % (int64_t)cap);
+            std::memcpy(host_out + 6 * (r * (size_t)max_rows + i), &ring[6 * (r * cap + slot)], 6 * sizeof(double));
+        }
+    *rows = (int32_t)k;
+    return KAMD_OK;
+}
+
+extern "C" int md_clear_samples(kamd_ctx *c)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    HIPCHK(c, launch_zero_i32(c->d.counters + 2, 1, c->stream));
+    return KAMD_OK;
+}
+
+extern "C" int md_observables_now(kamd_ctx *c, double *host_out)
 {
     if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");
     const size_t nr = c->reps.size();
@@ -1333,7 +1438,7 @@ extern "C" int md_profile(kamd_ctx *c, int32_t nsteps, double *host_out)
         if (fused[s]) {
             if (prec == KAMD_PREC_FP64 && !p4_ok) HIPCHK(c, launch_pack_pos(dd, c->stream));
             HIPCHK(c, launch_force_kd(dd, c->model, prec, dt, mir[1 - cur], c->md_base + (1 - par) * c->d.nrep,
-                                      p4[1 - cur], c->stream));
+                                      p4[1 - cur], false, c->stream));
             cur = 1 - cur;
             par = 1 - par;
             need_drift = false;

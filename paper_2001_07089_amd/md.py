@@ -34,7 +34,8 @@ EXPORTED = ("md_workspace_size", "md_admit", "md_init", "md_build_cells", "md_fo
             "md_step_nvt", "md_rdf", "md_msd", "md_observables", "md_thermostat_state", "md_sync",
             "md_import", "md_graph_capture", "md_graph_launch", "md_autotune", "md_set_list_params",
             "md_stats", "md_get_state", "md_set_state", "md_profile", "md_status", "md_last_error", "md_destroy",
-            "md_log_schedule", "md_set_temperature", "md_scale_velocities", "md_van_hove")
+            "md_log_schedule", "md_set_temperature", "md_scale_velocities", "md_van_hove",
+            "md_observables_now", "md_clear_samples")
 
 
 class KamdError(RuntimeError):
@@ -60,7 +61,7 @@ class Config(C.Structure):
     _fields_ = [("model", Model), ("precision", C.c_int32), ("dt", C.c_double), ("skin", C.c_double),
                 ("init_mode", C.c_int32), ("min_dist", C.c_double), ("cell_div", C.c_int32),
                 ("list_capacity", C.c_double), ("auto_sync", C.c_int32), ("dim", C.c_int32),
-                ("pe_unshifted", C.c_int32)]
+                ("pe_unshifted", C.c_int32), ("sample_every", C.c_int32), ("sample_capacity", C.c_int32)]
 
 
 _lib = None
@@ -85,7 +86,9 @@ def lib():
             "md_step_nvt": [P, i32, i32, i32, f64],
             "md_rdf": [P, f64, i32, P],
             "md_msd": [P, i32, i32, P],
-            "md_observables": [P, P],
+            "md_observables": [P, P, i32, C.POINTER(i32)],
+            "md_observables_now": [P, P],
+            "md_clear_samples": [P],
             "md_thermostat_state": [P, P],
             "md_sync": [P],
             "md_import": [P],
@@ -131,7 +134,8 @@ def make_model(eps=KA_EPS, sigma=KA_SIGMA, rc_factor=KA_RC_FACTOR) -> Model:
 
 
 def make_config(precision="fp64", dt=0.005, skin=0.3, init_mode=INIT_GIVEN, min_dist=0.8, cell_div=1,
-                list_capacity=0.0, auto_sync=1, model=None, dim=3, pe_unshifted=False) -> Config:
+                list_capacity=0.0, auto_sync=1, model=None, dim=3, pe_unshifted=False, sample_every=0,
+                sample_capacity=0) -> Config:
     c = Config()
     c.model = model if model is not None else make_model()
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -144,6 +148,8 @@ def make_config(precision="fp64", dt=0.005, skin=0.3, init_mode=INIT_GIVEN, min_
     c.auto_sync = int(auto_sync)
     c.dim = int(dim)
     c.pe_unshifted = 1 if pe_unshifted else 0
+    c.sample_every = int(sample_every)
+    c.sample_capacity = int(sample_capacity)
     return c
 
 
@@ -213,9 +219,21 @@ def md_msd(ctx, op: int, slot: int, out_ptr: int = 0):
     _check(lib().md_msd(ctx, int(op), int(slot), C.c_void_p(out_ptr or None)), ctx)
 
 
-def md_observables(ctx, n_rep: int):
+def md_observables(ctx, n_rep: int, max_rows: int):
+    """Sampled rows per replica: float64 [n_rep][rows][6] of {step, KE, PE, E_tot, T, W}."""
+    out = np.zeros((n_rep, max(int(max_rows), 1), 6))
+    rows = C.c_int32(0)
+    _check(lib().md_observables(ctx, out.ctypes.data, int(max_rows), C.byref(rows)), ctx)
+    return out[:, :rows.value].copy()
+
+
+def md_clear_samples(ctx):
+    _check(lib().md_clear_samples(ctx), ctx)
+
+
+def md_observables_now(ctx, n_rep: int):
     out = np.zeros((n_rep, 6))
-    _check(lib().md_observables(ctx, out.ctypes.data), ctx)
+    _check(lib().md_observables_now(ctx, out.ctypes.data), ctx)
     return out
 
 
@@ -323,7 +341,8 @@ class System:
 
     def __init__(self, replicas, precision="fp64", dt=0.005, skin=0.3, init="given",
                  positions=None, velocities=None, min_dist=0.8, cell_div=1, list_capacity=0.0,
-                 auto_sync=True, model=None, device="cuda", dim=3, pe_unshifted=False):
+                 auto_sync=True, model=None, device="cuda", dim=3, pe_unshifted=False, sample_every=0,
+                 sample_capacity=0):
         import torch
         self.torch = torch
         self.reps = make_replicas(replicas)
@@ -332,7 +351,7 @@ class System:
         self.offsets = [r.offset for r in self.reps]
         mode = {"given": INIT_GIVEN, "rsa": INIT_RSA, "lattice": INIT_LATTICE}[init]
         self.cfg = make_config(precision, dt, skin, mode, min_dist, cell_div, list_capacity,
-                               1 if auto_sync else 0, model, dim, pe_unshifted)
+                               1 if auto_sync else 0, model, dim, pe_unshifted, sample_every, sample_capacity)
         n = self.n_total
         # a dedicated stream: graph capture is not allowed on the legacy null
         # stream, and every allocation below is ordered on it
@@ -410,7 +429,16 @@ class System:
         md_scale_velocities(self.ctx, f)
 
     def observables(self):
-        return md_observables(self.ctx, self.n_rep)
+        """Observables of the current state, [n_rep][6] {KE, PE, W, T, E_tot, P}."""
+        return md_observables_now(self.ctx, self.n_rep)
+
+    def samples(self, max_rows=None):
+        """Rows of the observables ring, [n_rep][rows][6] {step, KE, PE, E_tot, T, W}."""
+        cap = self.cfg.sample_capacity or 1024
+        return md_observables(self.ctx, self.n_rep, cap if max_rows is None else max_rows)
+
+    def clear_samples(self):
+        md_clear_samples(self.ctx)
 
     def status(self):
         return md_status(self.ctx)
