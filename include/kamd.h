@@ -22,8 +22,12 @@
  *     Particle type is implied by that position; masses are 1 (Sec. II.B).
  *   - All work is enqueued on the caller's HIP stream given to md_init and
  *     returns without waiting, except where a function is marked "syncs".
- *   - The context owns its internal device memory (allocated in md_init,
- *     released in md_destroy).  Caller-owned buffers are only borrowed.
+ *   - Device memory: a context works in one workspace, a block of device
+ *     memory whose size md_workspace_size gives.  The caller may own it (for
+ *     example a torch uint8 tensor) and pass it to md_init; the library then
+ *     only borrows it and never frees it.  Given none, the library allocates
+ *     it and frees it in md_destroy.  Every other buffer (state arrays,
+ *     histograms, outputs) is the caller's and only borrowed.
  *   - One context must not be used from two host threads at once.
  */
 #ifndef KAMD_H
@@ -144,10 +148,15 @@ typedef struct {
                                0: no sampling.  Works inside captured graphs     */
     int32_t sample_capacity;/* rows of the ring buffer per replica (0 = 1024); the
                                oldest rows are overwritten                        */
+    int32_t msd_slots;      /* MSD origin slots (0 = 16); each holds 24 bytes per
+                               particle of the workspace                          */
 } kamd_config;
 
-/* Device bytes md_init would allocate for this configuration (host call, no
- * device needed).  Used for admission to HBM. */
+/* Bytes of device workspace a context of this configuration needs (host
+ * call, no device needed): the state and its scratch, tables, reductions,
+ * observables ring, MSD origins, RDF scratch and staging, then the cell
+ * arrays and the neighbour list at cfg's skin, cell division and list
+ * capacity.  Exactly the layout md_init carves.  Used for admission to HBM. */
 int md_workspace_size(const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
                       size_t *bytes);
 
@@ -160,8 +169,11 @@ int md_admit(const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
 typedef struct kamd_ctx kamd_ctx;
 
 /* Create a context on the current HIP device and stream `hip_stream`
- * (a hipStream_t; NULL = the null stream).  reps[] describes n_rep replicas
- * (host memory, copied).  st gives the caller-order device arrays: with
+ * (a hipStream_t; NULL = the null stream).  workspace: device memory of
+ * ws_bytes >= md_workspace_size bytes, 256-byte aligned, owned by the caller
+ * and used by nothing else while the context lives (KAMD_ENOMEM when too
+ * small); NULL: the library allocates its own.  reps[] describes n_rep
+ * replicas (host memory, copied).  st gives the caller-order device arrays: with
  * KAMD_INIT_GIVEN, x/y/z (in [0, L) per replica) and vx/vy/vz are read; with
  * the other init modes they are generated (RSA/lattice on the host from the
  * replica seed, velocities by the Maxwell-Boltzmann flow chart of Sec. II.E.1
@@ -171,14 +183,38 @@ typedef struct kamd_ctx kamd_ctx;
  * mass-free model), KAMD_EBOX (largest cutoff >= L/2), KAMD_ENOMEM,
  * KAMD_EHIP.  On error *out is NULL. */
 int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
-            const kamd_state *st, void *hip_stream);
+            const kamd_state *st, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Workspace the context needs now (host memory *bytes): more than it has
+ * after a refused md_set_list_params or md_autotune, or after a neighbour
+ * list outgrew its rows in a caller-owned workspace (those calls return
+ * KAMD_ENOMEM).  No device work. */
+int md_workspace_needed(kamd_ctx *ctx, size_t *bytes);
+
+/* Move the context into another caller-owned workspace (device, ws_bytes >=
+ * md_workspace_needed, 256-byte aligned, not the current one): the contents
+ * are copied, the old block is no longer used (freed when it was the
+ * library's own), and a captured graph is dropped (recapture).  Then repeat
+ * the call that was refused.  Syncs. */
+int md_set_workspace(kamd_ctx *ctx, void *workspace, size_t ws_bytes);
 
 /* Rebuild the cell lists and neighbour lists of every replica now: bin by
  * cell, stable counting sort of the internal particle order, pair list of all
  * partners within r_c(ab) + skin (the neighbour list of Sec. III.E; LAMMPS'
  * "bin" build, Sec. IV).  Rebuilds also happen automatically inside the step
  * functions whenever a particle has moved more than skin/2 since the last
- * build. */
+ * build.
+ *
+ * List overflow heals itself: a list that outgrows its rows sets
+ * KAMD_DEV_LIST_OVERFLOW on the device.  md_build_cells, md_forces,
+ * md_step_nve, md_step_nvt, md_import and md_set_state check for it before
+ * they return; the list then grows to the rows its build asked for (plus a
+ * quarter) and the call's work is redone (steps from the state the call
+ * started from), so those calls sync.  In a caller-owned workspace that is
+ * too small for the longer list they return KAMD_ENOMEM with the state of the
+ * call's start (md_workspace_needed, md_set_workspace, then call again).  A
+ * graph replay cannot heal: the bit stays for md_status; md_build_cells then
+ * grows the list, and the graph must be captured again. */
 int md_build_cells(kamd_ctx *ctx);
 
 /* Forces at the current positions, Eq. (KAFix) with the truncation of
@@ -191,7 +227,8 @@ int md_forces(kamd_ctx *ctx, uint32_t flags, double *obs_dev);
 
 /* nsteps velocity-Verlet steps in the order of Sec. II.D / Sec. III.E:
  * r += v dt + a dt^2/2, wrap, v += a dt/2, a = F(r), v += a dt/2
- * (Eqs. (velVerletPos),(velVerletVel)). */
+ * (Eqs. (velVerletPos),(velVerletVel)).  Syncs once at the end (the list
+ * check of md_build_cells). */
 int md_step_nve(kamd_ctx *ctx, int32_t nsteps);
 
 /* nsteps steps at constant N, V, T.
@@ -209,8 +246,10 @@ int md_step_nvt(kamd_ctx *ctx, int32_t nsteps, int32_t mode, int32_t n_reassign,
  * AB, BB; accumulated, the caller zeroes it): for every unique pair the
  * minimum-image distance r, bin = int(r / dr), counted when bin < n_bins;
  * AA and BB rows add 2 per pair, AB adds 1.  Requires n_bins*dr <= L/2 for
- * every replica (else KAMD_EINVAL).  Normalisation to g_ab(r) (Eqs. (gAA),
- * (gAB)) is left to the caller. */
+ * every replica and n_bins <= 5120 (else KAMD_EINVAL).  Normalisation to
+ * g_ab(r) (Eqs. (gAA), (gAB)) is left to the caller.  Asynchronous, allocates
+ * nothing (the cell grid is chosen on the device inside the workspace), and
+ * may be recorded in a stream capture. */
 int md_rdf(kamd_ctx *ctx, double dr, int32_t n_bins, uint64_t *hist_dev);
 
 /* Mean-square displacement (Eqs. (msdwithi),(msdtw)) with unwrapped

@@ -60,7 +60,6 @@ struct RepInfo {
     int32_t seg[2];        // segment indices (A, B)
     int32_t wave0, wave1;  // waves [wave0, wave1) of both segments
     int32_t nc;            // list cells per box edge
-    int32_t rdf_nc;        // cells per edge of the last RDF grid
     double skin;
     double disp_thr2;      // rebuild when max |dr|^2 exceeds this (real units)
     // pair constants in the u32 fixed-point length unit h = L / 2^32
@@ -72,8 +71,6 @@ struct RepInfo {
     double c48_h[3];       // 48 eps(ab) / h: converts the fixed-unit sum to a force
     double fix_k[3];       // 48 eps(ab) / h * FIX_SCALE
     double fx_to_len;      // h
-    int32_t rdf_cell0;     // first RDF cell of this replica
-    int32_t rdf_ncell;
 };
 
 // Pair model in real units (binary64), AA/AB/BB.
@@ -127,13 +124,17 @@ struct Dev {
     RepDyn *dyn;
     uint32_t *err;
     int32_t *counters;    // [0] = rebuilds, [1] = device step counter
-    // RDF scratch
+    // RDF scratch; rdf_grid[r] = {cells per edge, first cell, cells} of the
+    // last measurement's grid; rdf_count / rdf_start hold rdf_cells_cap cells
     int32_t *rdf_cell_of, *rdf_rank, *rdf_count, *rdf_start;
     double4 *rdf_pos;
+    int4 *rdf_grid;
+    int64_t rdf_cells_cap;
     const int32_t *rdf_block_rep;
     const int32_t *rdf_block_start;
-    // MSD origins [16][3][n_total] in caller order
+    // MSD origins [msd_slots][3][n_total] in caller order
     double *origin;
+    int32_t msd_slots;
     // sampled observables [nrep][ring_cap][6]: step, KE, PE, E_tot, T, W
     // (null when sampling is off); counters[2] counts the rows written
     double *ring;
@@ -200,7 +201,8 @@ hipError_t launch_store_pe_w(const Dev &d, double *out, hipStream_t s);
 // E_tot and T, then advance the row counter (counters[2]).
 hipError_t launch_sample(const Dev &d, int mask, hipStream_t s);
 
-hipError_t launch_rdf_prepare(const Dev &d, hipStream_t s);
+// Grid set-up on the device (k_rdf_setup), counting sort by RDF cell.
+hipError_t launch_rdf_prepare(const Dev &d, double rmax, hipStream_t s);
 hipError_t launch_rdf(const Dev &d, double dr, int nbins, int nblocks, uint64_t *hist, hipStream_t s);
 hipError_t launch_msd_set(const Dev &d, int slot, hipStream_t s);
 hipError_t launch_msd_measure(const Dev &d, int slot, hipStream_t s);

@@ -12,10 +12,42 @@
 
 namespace kamd {
 
-// RDF grid: per replica rdf_nc^3 cells (a planar system: one layer of
-// rdf_nc^2) of edge L/rdf_nc >= n_bins*dr, or >= n_bins*dr/2 where such cells
-// still hold several particles; both particle types together.
+// RDF grid: per replica nc^3 cells (a planar system: one layer of nc^2) of
+// edge L/nc >= n_bins*dr, or >= n_bins*dr/2 where such cells still hold
+// several particles; both particle types together.  The grid of replica r is
+// rdf_grid[r] = {nc, first cell, cells}, chosen on the device (k_rdf_setup),
+// so that a measurement needs no host round trip.
 // Counting sort into rdf_pos (replica-relative positions, w = type + 2*cell).
+
+// One thread: the grid of every replica for the histogram range r_max.  Cells
+// as wide as r_max, or half as wide where such cells would still hold six
+// particles or more on average; at most 2 n + 64 cells per replica (wider
+// cells stay correct, they only add candidates), so that every grid fits the
+// capacity the workspace reserves (2 n_total + 64 n_rep cells).
+__global__ void k_rdf_setup(Dev d, double rmax)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const bool planar = d.dim == 2;
+    const int cap = planar ? 4096 : 256;
+    auto cells = [&](int64_t k) { return planar ? k * k : k * k * k; };
+    int cell0 = 0;
+    for (int r = 0; r < d.nrep; ++r) {
+        const RepInfo &R = d.rep[r];
+        const double L = R.L;
+        const double hr = 0.5 * rmax;
+        const double per_cell = planar ? R.n / (L * L) * (hr * hr) : R.n / (L * L * L) * (hr * hr * hr);
+        const double per_range = per_cell >= 6.0 ? 2.0 : 1.0;
+        int nc = (int)fmax(1.0, fmin(floor(per_range * L / rmax), (double)cap));
+        const int64_t lim = 2 * (int64_t)R.n + 64;
+        int nmax = (int)floor(planar ? sqrt((double)lim) : cbrt((double)lim));
+        while (cells(nmax + 1) <= lim) ++nmax;
+        while (nmax > 1 && cells(nmax) > lim) --nmax;
+        nc = max(1, min(nc, nmax));
+        d.rdf_grid[r] = make_int4(nc, cell0, (int)cells(nc), 0);
+        cell0 += (int)cells(nc);
+    }
+}
+
 __global__ __launch_bounds__(BLOCK) void k_rdf_assign(Dev d)
 {
     const int w = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6);
@@ -23,11 +55,11 @@ __global__ __launch_bounds__(BLOCK) void k_rdf_assign(Dev d)
     const SegInfo &S = d.seg[d.wave_seg[w]];
     const int s = w * WAVE + lane_id();
     if (s - S.slot0 >= S.n) return;
-    const RepInfo &R = d.rep[S.rep];
-    const int nc = R.rdf_nc;
+    const int4 g = d.rdf_grid[S.rep];
+    const int nc = g.x;
     const uint4 m = d.mirror[s];
     const int cz = d.dim == 2 ? 0 : fix_cell(m.z, nc);
-    const int c = R.rdf_cell0 + (cz * nc + fix_cell(m.y, nc)) * nc + fix_cell(m.x, nc);
+    const int c = g.y + (cz * nc + fix_cell(m.y, nc)) * nc + fix_cell(m.x, nc);
     d.rdf_cell_of[s] = c;
     d.rdf_rank[s] = atomicAdd(&d.rdf_count[c], 1);
 }
@@ -38,12 +70,13 @@ __global__ __launch_bounds__(1024) void k_rdf_scan(Dev d)
 {
     __shared__ int part[1024];
     const RepInfo &R = d.rep[blockIdx.x];
-    const int n = R.rdf_ncell;
+    const int4 g = d.rdf_grid[blockIdx.x];
+    const int n = g.z;
     const int chunk = (n + 1023) / 1024;
     const int b = threadIdx.x * chunk;
     const int e = min(n, b + chunk);
     int sum = 0;
-    for (int c = b; c < e; ++c) sum += d.rdf_count[R.rdf_cell0 + c];
+    for (int c = b; c < e; ++c) sum += d.rdf_count[g.y + c];
     part[threadIdx.x] = sum;
     __syncthreads();
     for (int o = 1; o < 1024; o <<= 1) {
@@ -54,8 +87,8 @@ __global__ __launch_bounds__(1024) void k_rdf_scan(Dev d)
     }
     int run = (int)R.caller_off + part[threadIdx.x] - sum;
     for (int c = b; c < e; ++c) {
-        d.rdf_start[R.rdf_cell0 + c] = run;
-        run += d.rdf_count[R.rdf_cell0 + c];
+        d.rdf_start[g.y + c] = run;
+        run += d.rdf_count[g.y + c];
     }
 }
 
@@ -66,10 +99,9 @@ __global__ __launch_bounds__(BLOCK) void k_rdf_scatter(Dev d)
     const SegInfo &S = d.seg[d.wave_seg[w]];
     const int s = w * WAVE + lane_id();
     if (s - S.slot0 >= S.n) return;
-    const RepInfo &R = d.rep[S.rep];
     const int c = d.rdf_cell_of[s];
     const int t = d.rdf_start[c] + d.rdf_rank[s];
-    d.rdf_pos[t] = make_double4(d.x[s], d.y[s], d.z[s], (double)(S.type + 2 * (c - R.rdf_cell0)));
+    d.rdf_pos[t] = make_double4(d.x[s], d.y[s], d.z[s], (double)(S.type + 2 * (c - d.rdf_grid[S.rep].y)));
 }
 
 __device__ inline double min_image_branch(double dd, double L, double half)
@@ -109,7 +141,8 @@ __global__ __launch_bounds__(BLOCK) void k_rdf_hist(Dev d, double dr, int nbins,
         const int wi = (int)pi.w;
         const int ti = wi & 1;
         const int cl = wi >> 1;
-        const int nc = R.rdf_nc;
+        const int4 g = d.rdf_grid[rep];
+        const int nc = g.x;
         const int cx = cl % nc, cy = (cl / nc) % nc, cz = cl / (nc * nc);
         const double L = R.L;
         const double rmax = nbins * dr;
@@ -135,7 +168,7 @@ __global__ __launch_bounds__(BLOCK) void k_rdf_hist(Dev d, double dr, int nbins,
                     const double gx = whole ? 0.0 : cell_gap(ox, cx, cw, pi.x);
                     if (gx * gx + g2 > rp2) continue;
                     const int qx = (cx + ox + 2 * nc) % nc;
-                    const int c = R.rdf_cell0 + (qz * nc + qy) * nc + qx;
+                    const int c = g.y + (qz * nc + qy) * nc + qx;
                     const int st = d.rdf_start[c];
                     const int en = st + d.rdf_count[c];
                     for (int j = max(st, i + 1); j < en; ++j) {
@@ -249,8 +282,11 @@ __global__ void k_msd_finish(Dev d, double *out)
 
 static inline int nblk(const Dev &d) { return (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
 
-hipError_t launch_rdf_prepare(const Dev &d, hipStream_t s)
+hipError_t launch_rdf_prepare(const Dev &d, double rmax, hipStream_t s)
 {
+    hipLaunchKernelGGL(k_rdf_setup, dim3(1), dim3(64), 0, s, d, rmax);
+    hipError_t e = launch_zero_i32(d.rdf_count, d.rdf_cells_cap, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_rdf_assign, dim3(nblk(d)), dim3(BLOCK), 0, s, d);
     hipLaunchKernelGGL(k_rdf_scan, dim3(d.nrep), dim3(1024), 0, s, d);
     hipLaunchKernelGGL(k_rdf_scatter, dim3(nblk(d)), dim3(BLOCK), 0, s, d);

@@ -769,6 +769,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         row += words;
     }
     if (row > rows) {  // keep the force kernels inside the list
+        if (lane == 0) atomicMax(&d.counters[3], row);  // the rows a healing rebuild must provide
         const int w0 = min(bpart.x >= 0 ? kpart.x / 2 : kpart.x, rows);
         const int w1 = min(bpart.y >= 0 ? kpart.y / 2 : kpart.y, rows - w0);
         kpart.x = bpart.x >= 0 ? 2 * w0 : w0;

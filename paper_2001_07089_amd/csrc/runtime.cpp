@@ -20,6 +20,27 @@ using namespace kamd;
 
 static std::string g_init_error = "no error";
 
+// Layout of the replicas in slot order and the list grid for one choice of
+// skin and cell division.
+struct Plan {
+    std::vector<SegInfo> segs;
+    std::vector<RepInfo> rinfo;
+    std::vector<int32_t> wave_seg;
+    int32_t npad = 0, nwaves = 0, ncells = 0, rows = 0, n_total = 0;
+    int64_t ncells_wide = 0;  // the same count without 32-bit truncation
+    bool fp64 = false;        // FP64 precision: two packed position buffers
+};
+
+// Sizes of the fixed part of a workspace (independent of the list parameters).
+struct Shape {
+    size_t np = 0, nt = 0, nwaves = 0, nrep = 0, nseg = 0;
+    size_t rdf_blocks = 0;  // blocks of the RDF histogram kernel (BLOCK particles of one replica each)
+    size_t rdf_cells = 0;   // RDF cell capacity: 2 n + 64 per replica
+    size_t ring = 0;        // rows of the observables ring, all replicas
+    size_t msd_slots = 16;
+    bool fp64 = false;
+};
+
 struct kamd_ctx {
     kamd_config cfg{};
     Model model{};
@@ -33,18 +54,26 @@ struct kamd_ctx {
     hipStream_t stream = nullptr;
     int device = 0;
     Dev d{};
-    std::vector<void *> allocs;       // everything owned
-    void *cells_alloc[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // count, start, end, cell worklist
-    void *nbr_alloc = nullptr;
-    int64_t rdf_cells_cap = 0;
+    // The device workspace: one block, the caller's (borrowed) or the
+    // library's own when md_init was given none.  Layout: the fixed part
+    // (everything whose size does not depend on the list parameters), then
+    // the cell arrays and the neighbour list from list_off on.
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    bool ws_owned = false;
+    size_t list_off = 0;              // end of the fixed part
+    size_t need_bytes = 0;            // workspace the last refused request needed
+    int32_t rows_floor = 0;           // list rows a healed overflow asked for
     uint4 *mirror_alt = nullptr;      // second u32 mirror (fused force+drift steps)
     double4 *pos4_alt = nullptr;      // second packed FP64 position buffer (FP64 fused steps)
     uint32_t *md_base = nullptr;      // [2][n_rep] displacement maxima
     double *Q_dev = nullptr;
     double *rep_arg = nullptr;        // per-replica host arguments staged for a kernel
     double *obs_stage = nullptr;      // device [n_rep][4]
-    double *state_tmp = nullptr;      // device caller-order staging for checkpoints
+    double *state_tmp = nullptr;      // device caller-order staging: checkpoints, list-heal snapshots
     int32_t *img_tmp = nullptr;
+    RepDyn *dyn_snap = nullptr;       // thermostat scalars of a list-heal snapshot
+    int32_t *cnt_snap = nullptr;      // device counters of a list-heal snapshot
     int64_t step = 0;
     int64_t rebuilds_host = 0;
     double skin = 0.3;
@@ -52,6 +81,8 @@ struct kamd_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     int64_t graph_steps = 0;
+    Plan plan;                        // the current list parameters' layout
+    Shape shape;                      // sizes of the workspace's fixed part
     std::string err = "no error";
 };
 
@@ -130,6 +161,7 @@ static int validate(kamd_ctx *c, const kamd_config *cfg, const kamd_replica *rep
     if (cfg->pe_unshifted != 0 && cfg->pe_unshifted != 1) return fail(c, KAMD_EINVAL, "pe_unshifted must be 0 or 1");
     if (cfg->sample_every < 0 || cfg->sample_capacity < 0 || cfg->sample_capacity > (1 << 24))
         return fail(c, KAMD_EINVAL, "sample_every must be >= 0 and sample_capacity in [0, 2^24]");
+    if (cfg->msd_slots < 0 || cfg->msd_slots > 64) return fail(c, KAMD_EINVAL, "msd_slots must be in [0, 64]");
     if (!(cfg->model.rc_factor > 0.0)) return fail(c, KAMD_EINVAL, "rc_factor must be > 0");
     for (int p = 0; p < 3; ++p)
         if (!(cfg->model.sigma[p] > 0.0) || !std::isfinite(cfg->model.eps[p]))
@@ -151,14 +183,6 @@ static int validate(kamd_ctx *c, const kamd_config *cfg, const kamd_replica *rep
     return KAMD_OK;
 }
 
-struct Plan {
-    std::vector<SegInfo> segs;
-    std::vector<RepInfo> rinfo;
-    std::vector<int32_t> wave_seg;
-    int32_t npad = 0, nwaves = 0, ncells = 0, rows = 0, n_total = 0;
-    int64_t ncells_wide = 0;  // the same count without 32-bit truncation
-    bool fp64 = false;        // FP64 precision: two packed position buffers
-};
 
 // Limits of the list cell grid.  A segment holds at most 2^24 cells (nc is
 // lowered to fit: wider cells stay correct, they only add candidates), and a
@@ -180,7 +204,7 @@ static int ring_rows(const kamd_config *cfg)
 }
 
 static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_rep, double skin, int cell_div,
-                      Plan &P)
+                      Plan &P, int rows_floor = 0)
 {
     Model m;
     double rcmax;
@@ -269,7 +293,7 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
     P.npad = slot;
     P.nwaves = slot / WAVE;
     P.ncells = cell;
-    int rows = (int)std::ceil(cap * rows_need) + 32;
+    int rows = std::max((int)std::ceil(cap * rows_need) + 32, rows_floor);
     rows = (rows + LIST_ROW_ALIGN - 1) / LIST_ROW_ALIGN * LIST_ROW_ALIGN;
     P.rows = rows;
 }
@@ -282,24 +306,139 @@ static int plan_fits(kamd_ctx *c, const Plan &P)
     return KAMD_OK;
 }
 
-// Bytes of device memory for a plan.
-static size_t plan_bytes(const Plan &P, int n_rep)
+// ------------------------------------------------------------------ memory
+// Bump allocator over the device workspace (256-byte aligned pieces).  With no
+// base it only measures: md_workspace_size and md_admit run the very carve
+// that md_init performs, so the sizes they report are the sizes used.
+struct Carve {
+    char *base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+        off += std::max<size_t>(count, 1) * sizeof(T);
+        return p;
+    }
+};
+
+static int msd_slots_of(const kamd_config *cfg) { return cfg->msd_slots > 0 ? cfg->msd_slots : 16; }
+
+static Shape shape_of(const kamd_config *cfg, const kamd_replica *reps, int n_rep, const Plan &P)
 {
-    const size_t np = P.npad, nt = P.n_total;
-    size_t b = 0;
-    b += 2 * (9 * 8 + 3 * 4 + 4 + 16) * np;  // state + scratch
-    b += 16 * np + 16 * LIST_UNROLL;           // mbuild, tail of the sorted mirror
-    b += (P.fp64 ? 64 : 0) * np;               // packed FP64 positions, two buffers
-    b += 4 * np * 3;                           // cell_of, rank, order
-    b += 4 * np;                               // nlen
-    b += 4 * (size_t)P.ncells_wide * 3 * CELL_SUBX;  // count/start/end per sub-cell
-    b += 4 * (size_t)P.rows * np;              // neighbour list
-    b += (8 + 8 + 4 + 32) * (size_t)P.nwaves;  // kmax, lbase, disp, wred
-    b += (sizeof(SegInfo) + sizeof(RepInfo)) * 2 * (size_t)n_rep + 4 * ((size_t)P.nwaves + P.ncells_wide);
-    b += 3 * 8 * nt;                           // one MSD origin (more on demand)
-    b += 8 * (size_t)n_rep;                    // per-replica kernel arguments
-    b += 4 * (size_t)P.nwaves;                 // rebuild worklist
-    return b;
+    Shape z;
+    z.np = P.npad;
+    z.nt = P.n_total;
+    z.nwaves = P.nwaves;
+    z.nrep = n_rep;
+    z.nseg = P.segs.size();
+    for (int r = 0; r < n_rep; ++r) {
+        z.rdf_blocks += (reps[r].n + BLOCK - 1) / BLOCK;
+        z.rdf_cells += 2 * (size_t)reps[r].n + 64;
+    }
+    z.ring = (size_t)ring_rows(cfg) * n_rep;
+    z.msd_slots = msd_slots_of(cfg);
+    z.fp64 = cfg->precision == KAMD_PREC_FP64;
+    return z;
+}
+
+// Pieces of the fixed part that the context holds outside Dev.
+struct CtxBufs {
+    uint4 *mirror_alt = nullptr;
+    double4 *pos4_alt = nullptr;
+    uint32_t *md_base = nullptr;
+    double *Q_dev = nullptr, *rep_arg = nullptr, *obs_stage = nullptr, *state_tmp = nullptr;
+    int32_t *img_tmp = nullptr;
+    RepDyn *dyn_snap = nullptr;
+    int32_t *cnt_snap = nullptr;
+    int32_t *rdf_block_rep = nullptr, *rdf_block_start = nullptr;
+};
+
+// The fixed part: slot-order state and its permutation scratch, layout
+// tables, rebuild bookkeeping, reductions, observables ring, MSD origins, RDF
+// scratch, caller-order staging.
+static void carve_fixed(Dev &d, CtxBufs &b, const Shape &z, Carve &k)
+{
+    const size_t np = z.np, nt = z.nt;
+    double **f64[] = {&d.x, &d.y, &d.z, &d.vx, &d.vy, &d.vz, &d.ax, &d.ay, &d.az,
+                      &d.sx, &d.sy, &d.sz, &d.svx, &d.svy, &d.svz, &d.sax, &d.say, &d.saz};
+    for (auto p : f64) *p = k.take<double>(np);
+    d.img = k.take<int32_t>(3 * np);
+    d.simg = k.take<int32_t>(3 * np);
+    d.id = k.take<int32_t>(np);
+    d.sid = k.take<int32_t>(np);
+    d.mirror = k.take<uint4>(np);
+    d.mbuild = k.take<uint4>(np);
+    d.smirror = k.take<uint4>(np + LIST_UNROLL);  // the list scan reads up to 7 past a range
+    b.mirror_alt = k.take<uint4>(np);
+    d.pos4 = z.fp64 ? k.take<double4>(np) : nullptr;
+    b.pos4_alt = z.fp64 ? k.take<double4>(np) : nullptr;
+    d.seg = k.take<SegInfo>(z.nseg);
+    d.rep = k.take<RepInfo>(z.nrep);
+    d.wave_seg = k.take<int32_t>(z.nwaves);
+    d.cell_of = k.take<int32_t>(np);
+    d.rank = k.take<int32_t>(np);
+    d.order = k.take<int32_t>(np);
+    d.nlen = k.take<int32_t>(np);
+    d.rb_force = k.take<int32_t>(z.nrep);
+    d.rb_any = k.take<int32_t>(2);
+    d.rb_wlist = k.take<int32_t>(z.nwaves);
+    b.md_base = k.take<uint32_t>(2 * z.nrep);
+    d.kmax = k.take<int2>(z.nwaves);
+    d.lbase = k.take<int2>(z.nwaves);
+    d.wred = k.take<double>(4 * z.nwaves);
+    d.rsum = k.take<double>(4 * z.nrep);
+    d.obs = k.take<double>(8 * z.nrep);
+    d.dyn = k.take<RepDyn>(z.nrep);
+    d.err = k.take<uint32_t>(4);
+    d.counters = k.take<int32_t>(8);
+    b.Q_dev = k.take<double>(z.nrep);
+    b.rep_arg = k.take<double>(z.nrep);
+    b.obs_stage = k.take<double>(4 * z.nrep);
+    d.ring = z.ring ? k.take<double>(6 * z.ring) : nullptr;
+    d.origin = k.take<double>(z.msd_slots * 3 * nt);
+    d.rdf_cell_of = k.take<int32_t>(np);
+    d.rdf_rank = k.take<int32_t>(np);
+    d.rdf_pos = k.take<double4>(nt);
+    d.rdf_count = k.take<int32_t>(z.rdf_cells);
+    d.rdf_start = k.take<int32_t>(z.rdf_cells);
+    d.rdf_grid = k.take<int4>(z.nrep);
+    b.rdf_block_rep = k.take<int32_t>(z.rdf_blocks);
+    b.rdf_block_start = k.take<int32_t>(z.rdf_blocks);
+    b.state_tmp = k.take<double>(9 * nt);
+    b.img_tmp = k.take<int32_t>(3 * nt);
+    b.dyn_snap = k.take<RepDyn>(z.nrep);
+    b.cnt_snap = k.take<int32_t>(8);
+}
+
+// The part that depends on the list parameters: per sub-cell counters and
+// ranges, the rebuild cell worklist and the neighbour list.
+static void carve_list(Dev &d, const Plan &P, Carve &k)
+{
+    const size_t nsub = (size_t)CELL_SUBX * P.ncells;
+    d.cell_count = k.take<int32_t>(nsub);
+    d.cell_start = k.take<int32_t>(nsub);
+    d.cell_end = k.take<int32_t>(nsub);
+    d.rb_clist = k.take<int32_t>(P.ncells);
+    d.nbr = k.take<int32_t>((size_t)P.rows * P.npad);
+}
+
+static size_t fixed_bytes(const Shape &z)
+{
+    Dev d{};
+    CtxBufs b;
+    Carve k;
+    carve_fixed(d, b, z, k);
+    return (k.off + 255) & ~(size_t)255;
+}
+
+static size_t list_bytes(const Plan &P)
+{
+    Dev d{};
+    Carve k;
+    carve_list(d, P, k);
+    return k.off;
 }
 
 extern "C" int md_workspace_size(const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep, size_t *bytes)
@@ -311,7 +450,7 @@ extern "C" int md_workspace_size(const kamd_config *cfg, const kamd_replica *rep
     make_plan(cfg, reps, n_rep, list_skin(cfg), cfg->cell_div <= 0 ? 1 : cfg->cell_div, P);
     rc = plan_fits(nullptr, P);
     if (rc) return rc;
-    *bytes = plan_bytes(P, n_rep);
+    *bytes = fixed_bytes(shape_of(cfg, reps, n_rep, P)) + list_bytes(P);
     return KAMD_OK;
 }
 
@@ -319,55 +458,32 @@ extern "C" int md_admit(const kamd_config *cfg, const kamd_replica *reps, int32_
                         int32_t *admitted, int32_t *n_admitted)
 {
     if (!cfg || !reps || n_rep <= 0 || !admitted) return fail(nullptr, KAMD_EINVAL, "bad arguments to md_admit");
-    size_t used = 0;
     int cnt = 0;
     std::vector<kamd_replica> acc;
+    int64_t off = 0;
     for (int r = 0; r < n_rep; ++r) {
         kamd_replica k = reps[r];
-        k.offset = 0;
-        for (auto &a : acc) k.offset += a.n;
+        k.offset = off;
         acc.push_back(k);
-        Plan P;
-        int v = validate(nullptr, cfg, acc.data(), (int)acc.size());
         size_t b = 0;
+        int v = validate(nullptr, cfg, acc.data(), (int)acc.size());
         if (v == KAMD_OK) {
+            Plan P;
             make_plan(cfg, acc.data(), (int)acc.size(), list_skin(cfg), cfg->cell_div <= 0 ? 1 : cfg->cell_div, P);
             if (P.ncells_wide > MAX_PLAN_CELLS) v = KAMD_EINVAL;
-            b = plan_bytes(P, (int)acc.size());
+            else b = fixed_bytes(shape_of(cfg, acc.data(), (int)acc.size(), P)) + list_bytes(P);
         }
         if (v == KAMD_OK && b <= budget) {
             admitted[r] = 1;
-            used = b;
+            off += k.n;
             ++cnt;
         } else {
             admitted[r] = 0;
             acc.pop_back();
         }
     }
-    (void)used;
     if (n_admitted) *n_admitted = cnt;
     return KAMD_OK;
-}
-
-// ------------------------------------------------------------------ memory
-template <typename T>
-static int dalloc(kamd_ctx *c, T **p, size_t count)
-{
-    void *q = nullptr;
-    if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&q, count * sizeof(T));
-    if (e != hipSuccess) return fail(c, KAMD_ENOMEM, "hipMalloc(%zu bytes): %s", count * sizeof(T), hipGetErrorString(e));
-    c->allocs.push_back(q);
-    *p = (T *)q;
-    return KAMD_OK;
-}
-
-static void dfree(kamd_ctx *c, void *p)
-{
-    if (!p) return;
-    auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
-    if (it != c->allocs.end()) c->allocs.erase(it);
-    (void)hipFree(p);
 }
 
 #define TRY(x)                 \
@@ -375,6 +491,105 @@ static void dfree(kamd_ctx *c, void *p)
         int r_ = (x);          \
         if (r_) return r_;     \
     } while (0)
+
+// Point Dev and the context's buffers into the workspace: the fixed part at
+// its start, the cell arrays and the list of plan P from list_off on.
+static void bind_workspace(kamd_ctx *c, const Plan &P)
+{
+    Dev &d = c->d;
+    CtxBufs b;
+    Carve k;
+    k.base = c->ws;
+    carve_fixed(d, b, c->shape, k);
+    c->list_off = (k.off + 255) & ~(size_t)255;
+    c->mirror_alt = b.mirror_alt;
+    c->pos4_alt = b.pos4_alt;
+    c->md_base = b.md_base;
+    d.maxdisp = b.md_base;
+    c->Q_dev = b.Q_dev;
+    c->rep_arg = b.rep_arg;
+    c->obs_stage = b.obs_stage;
+    c->state_tmp = b.state_tmp;
+    c->img_tmp = b.img_tmp;
+    c->dyn_snap = b.dyn_snap;
+    c->cnt_snap = b.cnt_snap;
+    d.rdf_block_rep = b.rdf_block_rep;
+    d.rdf_block_start = b.rdf_block_start;
+    Carve kl;
+    kl.base = c->ws + c->list_off;
+    carve_list(d, P, kl);
+    d.npad_total = P.npad;
+    d.n_total = P.n_total;
+    d.nwaves = P.nwaves;
+    d.nrep = (int32_t)c->reps.size();
+    d.dim = dim_of(&c->cfg);
+    d.rows = P.rows;
+    d.ncells = P.ncells;
+    d.rdf_cells_cap = (int64_t)c->shape.rdf_cells;
+    d.ring_cap = ring_rows(&c->cfg);
+    d.msd_slots = (int32_t)c->shape.msd_slots;
+}
+
+static size_t need_for(const kamd_ctx *c, const Plan &P) { return c->list_off + list_bytes(P); }
+
+// Zero what the kernels read before they write it (the fixed part).
+static int init_fixed(kamd_ctx *c)
+{
+    Dev &d = c->d;
+    const int64_t np = d.npad_total, nr = d.nrep, nw = d.nwaves;
+    double *f64[] = {d.x, d.y, d.z, d.vx, d.vy, d.vz, d.ax, d.ay, d.az,
+                     d.sx, d.sy, d.sz, d.svx, d.svy, d.svz, d.sax, d.say, d.saz};
+    for (auto p : f64) HIPCHK(c, launch_zero_f64(p, np, c->stream));
+    HIPCHK(c, launch_zero_i32(d.img, 3 * np, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.mirror, 4 * np, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.mbuild, 4 * np, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.smirror, 4 * (np + LIST_UNROLL), c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)c->mirror_alt, 4 * np, c->stream));
+    HIPCHK(c, launch_zero_i32(d.nlen, np, c->stream));
+    HIPCHK(c, launch_zero_i32(d.rb_force, nr, c->stream));
+    HIPCHK(c, launch_zero_i32(d.rb_any, 2, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)c->md_base, 2 * nr, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.kmax, 2 * nw, c->stream));
+    HIPCHK(c, launch_fill_i32((int32_t *)d.lbase, 2 * nw, -1, c->stream));
+    HIPCHK(c, launch_zero_f64(d.wred, 4 * nw, c->stream));
+    HIPCHK(c, launch_zero_f64((double *)d.dyn, (int64_t)(sizeof(RepDyn) / 8) * nr, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.err, 4, c->stream));
+    HIPCHK(c, launch_zero_i32(d.counters, 8, c->stream));
+    if (d.ring) HIPCHK(c, launch_zero_f64(d.ring, 6 * (int64_t)c->shape.ring, c->stream));
+    return KAMD_OK;
+}
+
+// Zero the cell counters and the list of the current plan (the counting sort
+// expects zero counters; the list kernel overwrites whole rows).
+static int init_list(kamd_ctx *c)
+{
+    Dev &d = c->d;
+    HIPCHK(c, launch_zero_i32(d.cell_count, (int64_t)CELL_SUBX * d.ncells, c->stream));
+    HIPCHK(c, launch_zero_i32(d.nbr, (int64_t)d.rows * d.npad_total, c->stream));
+    return KAMD_OK;
+}
+
+// Make the workspace hold `need` bytes with the fixed part preserved.  A
+// library-owned workspace is reallocated; a caller-owned one cannot grow
+// here: KAMD_ENOMEM, and md_workspace_needed reports the size.
+static int grow_workspace(kamd_ctx *c, size_t need)
+{
+    if (need <= c->ws_bytes) return KAMD_OK;
+    c->need_bytes = std::max(c->need_bytes, need);
+    if (!c->ws_owned)
+        return fail(c, KAMD_ENOMEM, "the caller's workspace of %zu bytes is too small: %zu needed "
+                    "(md_workspace_needed, md_set_workspace)", c->ws_bytes, need);
+    char *nw = nullptr;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const hipError_t e = hipMalloc((void **)&nw, need);
+    if (e != hipSuccess) return fail(c, KAMD_ENOMEM, "hipMalloc(%zu bytes): %s", need, hipGetErrorString(e));
+    HIPCHK(c, hipMemcpyAsync(nw, c->ws, c->list_off, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    (void)hipFree(c->ws);
+    c->ws = nw;
+    c->ws_bytes = need;
+    return KAMD_OK;
+}
 
 static int upload_tables(kamd_ctx *c)
 {
@@ -393,121 +608,6 @@ static void drop_graph(kamd_ctx *c)
     c->graph_exec = nullptr;
     c->graph = nullptr;
     c->graph_steps = 0;
-}
-
-// (Re)allocate what depends on the list parameters: cell arrays, cell->segment
-// table and the neighbour list.
-static int alloc_list_buffers(kamd_ctx *c, const Plan &P)
-{
-    Dev &d = c->d;
-    for (int k = 0; k < 5; ++k) {
-        dfree(c, c->cells_alloc[k]);
-        c->cells_alloc[k] = nullptr;
-    }
-    dfree(c, c->nbr_alloc);
-    c->nbr_alloc = nullptr;
-    int32_t *cc, *cs, *ce, *cl;
-    const size_t nsub = (size_t)CELL_SUBX * P.ncells;  // counters and ranges per sub-cell
-    TRY(dalloc(c, &cc, nsub));
-    TRY(dalloc(c, &cs, nsub));
-    TRY(dalloc(c, &ce, nsub));
-    TRY(dalloc(c, &cl, P.ncells));
-    c->cells_alloc[0] = cc;
-    c->cells_alloc[1] = cs;
-    c->cells_alloc[2] = ce;
-    c->cells_alloc[3] = cl;
-    d.cell_count = cc;
-    d.cell_start = cs;
-    d.cell_end = ce;
-    d.rb_clist = cl;
-    int32_t *nb;
-    TRY(dalloc(c, &nb, (size_t)P.rows * P.npad));
-    c->nbr_alloc = nb;
-    d.nbr = nb;
-    d.rows = P.rows;
-    d.ncells = P.ncells;
-    HIPCHK(c, launch_zero_i32(cc, (int64_t)nsub, c->stream));
-    HIPCHK(c, launch_zero_i32(nb, (int64_t)P.rows * P.npad, c->stream));
-    return KAMD_OK;
-}
-
-static int alloc_all(kamd_ctx *c, const Plan &P)
-{
-    Dev &d = c->d;
-    const size_t np = P.npad;
-    d.npad_total = P.npad;
-    d.n_total = P.n_total;
-    d.nwaves = P.nwaves;
-    d.nrep = (int32_t)c->reps.size();
-    d.dim = dim_of(&c->cfg);
-    double **f64[] = {&d.x, &d.y, &d.z, &d.vx, &d.vy, &d.vz, &d.ax, &d.ay, &d.az,
-                      &d.sx, &d.sy, &d.sz, &d.svx, &d.svy, &d.svz, &d.sax, &d.say, &d.saz};
-    for (auto p : f64) TRY(dalloc(c, p, np));
-    TRY(dalloc(c, &d.img, 3 * np));
-    TRY(dalloc(c, &d.simg, 3 * np));
-    TRY(dalloc(c, &d.id, np));
-    TRY(dalloc(c, &d.sid, np));
-    TRY(dalloc(c, &d.mirror, np));
-    TRY(dalloc(c, &d.mbuild, np));
-    d.pos4 = nullptr;
-    c->pos4_alt = nullptr;
-    if (c->cfg.precision == KAMD_PREC_FP64) {
-        TRY(dalloc(c, &d.pos4, np));
-        TRY(dalloc(c, &c->pos4_alt, np));
-    }
-    TRY(dalloc(c, &d.smirror, np + LIST_UNROLL));  // the list scan reads up to 7 past a range
-    SegInfo *sg;
-    RepInfo *ri;
-    int32_t *ws;
-    TRY(dalloc(c, &sg, c->segs.size()));
-    TRY(dalloc(c, &ri, c->rinfo.size()));
-    TRY(dalloc(c, &ws, P.nwaves));
-    d.seg = sg;
-    d.rep = ri;
-    d.wave_seg = ws;
-    TRY(dalloc(c, &d.cell_of, np));
-    TRY(dalloc(c, &d.rank, np));
-    TRY(dalloc(c, &d.order, np));
-    TRY(dalloc(c, &d.nlen, np));
-    TRY(dalloc(c, &d.rb_force, d.nrep));
-    TRY(dalloc(c, &d.rb_any, 2));
-    TRY(dalloc(c, &d.rb_wlist, P.nwaves));
-    TRY(dalloc(c, &c->md_base, 2 * (size_t)d.nrep));
-    d.maxdisp = c->md_base;
-    TRY(dalloc(c, &c->mirror_alt, np));
-    TRY(dalloc(c, &d.kmax, P.nwaves));
-    TRY(dalloc(c, &d.lbase, P.nwaves));
-    TRY(dalloc(c, &d.wred, 4 * (size_t)P.nwaves));
-    TRY(dalloc(c, &d.rsum, 4 * (size_t)d.nrep));
-    TRY(dalloc(c, &d.obs, 8 * (size_t)d.nrep));
-    TRY(dalloc(c, &d.dyn, d.nrep));
-    TRY(dalloc(c, &d.err, 4));
-    TRY(dalloc(c, &d.counters, 8));
-    TRY(dalloc(c, &c->Q_dev, d.nrep));
-    TRY(dalloc(c, &c->rep_arg, d.nrep));
-    TRY(dalloc(c, &c->obs_stage, 4 * (size_t)d.nrep));
-    d.ring_cap = ring_rows(&c->cfg);
-    d.ring = nullptr;
-    if (d.ring_cap > 0) TRY(dalloc(c, &d.ring, 6 * (size_t)d.nrep * d.ring_cap));
-    // zero everything that is read before written
-    for (auto p : f64) HIPCHK(c, launch_zero_f64(*p, np, c->stream));
-    HIPCHK(c, launch_zero_i32(d.img, 3 * np, c->stream));
-    HIPCHK(c, launch_zero_i32((int32_t *)d.mirror, 4 * np, c->stream));
-    HIPCHK(c, launch_zero_i32((int32_t *)d.mbuild, 4 * np, c->stream));
-    HIPCHK(c, launch_zero_i32((int32_t *)d.smirror, 4 * (np + LIST_UNROLL), c->stream));
-    HIPCHK(c, launch_zero_i32(d.nlen, np, c->stream));
-    HIPCHK(c, launch_zero_i32(d.rb_force, d.nrep, c->stream));
-    HIPCHK(c, launch_zero_i32(d.rb_any, 2, c->stream));
-    HIPCHK(c, launch_zero_i32((int32_t *)c->md_base, 2 * (int64_t)d.nrep, c->stream));
-    HIPCHK(c, launch_zero_i32((int32_t *)c->mirror_alt, 4 * np, c->stream));
-    HIPCHK(c, launch_zero_i32((int32_t *)d.kmax, 2 * (int64_t)P.nwaves, c->stream));
-    HIPCHK(c, launch_fill_i32((int32_t *)d.lbase, 2 * (int64_t)P.nwaves, -1, c->stream));
-    HIPCHK(c, launch_zero_f64(d.wred, 4 * (int64_t)P.nwaves, c->stream));
-    HIPCHK(c, launch_zero_f64((double *)d.dyn, 8 * (int64_t)d.nrep, c->stream));
-    HIPCHK(c, launch_zero_i32((int32_t *)d.err, 4, c->stream));
-    HIPCHK(c, launch_zero_i32(d.counters, 8, c->stream));
-    TRY(alloc_list_buffers(c, P));
-    return KAMD_OK;
 }
 
 // ---------------------------------------------------------- initial states
@@ -766,33 +866,139 @@ static int set_Q(kamd_ctx *c, double tau)
     return KAMD_OK;
 }
 
+static int apply_list_params(kamd_ctx *c, double skin, int cell_div, bool first);
+
+// ---------------------------------------------------- list self-healing
+// A neighbour list that outgrows its rows sets KAMD_DEV_LIST_OVERFLOW and
+// records in counters[3] the rows its build needed; the force kernels then
+// stay inside the truncated list, so that step's forces are wrong.  Eager
+// calls check for it before they return: the list gets the rows asked for
+// (plus a quarter), and the call's work is redone from the state it started
+// from.  Graph replays cannot heal: the bit stays for md_status, and
+// md_build_cells then grows the list (the caller recaptures).
+
+// The dynamical state at the start of an eager step call, in caller order.
+static int snapshot_save(kamd_ctx *c)
+{
+    const Dev &d = c->d;
+    const size_t nt = d.n_total;
+    double *a[9];
+    for (int k = 0; k < 9; ++k) a[k] = c->state_tmp + k * nt;
+    HIPCHK(c, launch_export(d, a, c->img_tmp, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->dyn_snap, d.dyn, sizeof(RepDyn) * c->reps.size(), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->cnt_snap, d.counters, 32, hipMemcpyDeviceToDevice, c->stream));
+    return KAMD_OK;
+}
+
+static int snapshot_restore(kamd_ctx *c)
+{
+    const Dev &d = c->d;
+    const size_t nt = d.n_total;
+    const double *a[9];
+    for (int k = 0; k < 9; ++k) a[k] = c->state_tmp + k * nt;
+    HIPCHK(c, launch_import(d, a, c->img_tmp, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.dyn, c->dyn_snap, sizeof(RepDyn) * c->reps.size(), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(d.counters, c->cnt_snap, 32, hipMemcpyDeviceToDevice, c->stream));
+    return force_rebuild_all(c);
+}
+
+// Waits for the stream.  redo: a list overflowed, the bit is cleared and the
+// list has grown to the rows its build asked for.
+static int heal_list(kamd_ctx *c, bool &redo)
+{
+    redo = false;
+    uint32_t w = 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(&w, c->d.err, 4, hipMemcpyDeviceToHost));
+    if (!(w & KAMD_DEV_LIST_OVERFLOW)) return KAMD_OK;
+    int32_t cnt[8];
+    HIPCHK(c, hipMemcpy(cnt, c->d.counters, 32, hipMemcpyDeviceToHost));
+    const uint32_t keep = w & ~(uint32_t)KAMD_DEV_LIST_OVERFLOW;
+    const int32_t zero = 0;
+    HIPCHK(c, hipMemcpy(c->d.err, &keep, 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d.counters + 3, &zero, 4, hipMemcpyHostToDevice));
+    const int need = std::max(cnt[3], c->d.rows + 1);
+    c->rows_floor = std::max(c->rows_floor, need + need / 4 + LIST_ROW_ALIGN);
+    TRY(apply_list_params(c, c->skin, c->cell_div, false));
+    redo = true;
+    return KAMD_OK;
+}
+
+constexpr int HEAL_ATTEMPTS = 4;
+
+// Rebuild the lists (and with `force`, evaluate forces) until no list overflows.
+static int heal_build(kamd_ctx *c, bool force, bool energy)
+{
+    for (int attempt = 0;; ++attempt) {
+        if (force) TRY(forces(c, energy));
+        else TRY(rebuild_chain(c, c->d));
+        bool redo = false;
+        TRY(heal_list(c, redo));
+        if (!redo) return KAMD_OK;
+        if (attempt + 1 >= HEAL_ATTEMPTS)
+            return fail(c, KAMD_EDEVICE, "neighbour list still overflows after %d rebuilds", attempt + 1);
+    }
+}
+
+static int heal_forces(kamd_ctx *c, bool energy) { return heal_build(c, true, energy); }
+
+// Eager steps, redone from the call's starting state while a list overflows.
+// On failure (a caller-owned workspace too small for the grown list) the state
+// is that of the start of the call.
+static int heal_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb)
+{
+    TRY(snapshot_save(c));
+    for (int attempt = 0;; ++attempt) {
+        TRY(enqueue_steps(c, nsteps, ensemble, mode, nb, false));
+        bool redo = false;
+        const int rc = heal_list(c, redo);
+        if (rc) {
+            (void)snapshot_restore(c);
+            return rc;
+        }
+        if (!redo) return KAMD_OK;
+        if (attempt + 1 >= HEAL_ATTEMPTS)
+            return fail(c, KAMD_EDEVICE, "neighbour list still overflows after %d rebuilds", attempt + 1);
+        TRY(snapshot_restore(c));
+    }
+}
+
 // ------------------------------------------------------------------ C ABI
 extern "C" const char *md_last_error(const kamd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
 
+// Adopt a skin and cell division (and the list rows of a healed overflow):
+// the plan, the tables, and (after md_init) the cell and list part of the
+// workspace, which grows when it must.  Forces a full rebuild at the next
+// step and drops a captured graph, whose pointers it may invalidate.
 static int apply_list_params(kamd_ctx *c, double skin, int cell_div, bool first)
 {
     if (!(skin >= 0.0)) return fail(c, KAMD_EINVAL, "skin must be >= 0");
     if (cell_div < 1 || cell_div > 2) return fail(c, KAMD_EINVAL, "cell_div must be 1 or 2");
     Plan P;
-    make_plan(&c->cfg, c->reps.data(), (int)c->reps.size(), skin, cell_div, P);
+    make_plan(&c->cfg, c->reps.data(), (int)c->reps.size(), skin, cell_div, P, c->rows_floor);
     TRY(plan_fits(c, P));
+    if (!first) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        TRY(grow_workspace(c, need_for(c, P)));
+    }
     c->skin = skin;
     c->cell_div = cell_div;
     c->segs = P.segs;
     c->rinfo = P.rinfo;
     c->wave_seg = P.wave_seg;
+    c->plan = P;
     if (!first) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        TRY(alloc_list_buffers(c, P));
+        drop_graph(c);
+        bind_workspace(c, P);
+        TRY(init_list(c));
         TRY(upload_tables(c));
         TRY(force_rebuild_all(c));
-        drop_graph(c);
     }
     return KAMD_OK;
 }
 
 extern "C" int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
-                       const kamd_state *st, void *hip_stream)
+                       const kamd_state *st, void *workspace, size_t ws_bytes, void *hip_stream)
 {
     if (!out) return fail(nullptr, KAMD_EINVAL, "out is null");
     *out = nullptr;
@@ -815,9 +1021,30 @@ extern "C" int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replic
         for (int p = 0; p < 3; ++p) c->model.vshift[p] = 0.0;
     int r = [&]() -> int {
         TRY(apply_list_params(c, list_skin(cfg), cfg->cell_div <= 0 ? 1 : cfg->cell_div, true));
-        Plan P;
-        make_plan(&c->cfg, c->reps.data(), n_rep, c->skin, c->cell_div, P);
-        TRY(alloc_all(c, P));
+        const Plan &P = c->plan;
+        c->shape = shape_of(cfg, reps, n_rep, P);
+        const size_t need = fixed_bytes(c->shape) + list_bytes(P);
+        if (workspace) {
+            if ((uintptr_t)workspace % 256) return fail(c, KAMD_EINVAL, "workspace must be 256-byte aligned");
+            if (ws_bytes < need) {
+                c->need_bytes = need;
+                return fail(c, KAMD_ENOMEM, "workspace of %zu bytes is too small: md_workspace_size gives %zu",
+                            ws_bytes, need);
+            }
+            c->ws = (char *)workspace;
+            c->ws_bytes = ws_bytes;
+        } else {
+            const hipError_t e = hipMalloc((void **)&c->ws, need);
+            if (e != hipSuccess) {
+                c->ws = nullptr;
+                return fail(c, KAMD_ENOMEM, "hipMalloc(%zu bytes): %s", need, hipGetErrorString(e));
+            }
+            c->ws_bytes = need;
+            c->ws_owned = true;
+        }
+        bind_workspace(c, P);
+        TRY(init_fixed(c));
+        TRY(init_list(c));
         TRY(upload_tables(c));
         // slot -> caller index
         std::vector<int32_t> ids(P.npad, -1);
@@ -833,14 +1060,10 @@ extern "C" int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replic
                 c->rdf_block_rep.push_back(q);
                 c->rdf_block_start.push_back((int32_t)(c->reps[q].offset + i));
             }
-        int32_t *brep, *bst;
-        TRY(dalloc(c, &brep, c->rdf_block_rep.size()));
-        TRY(dalloc(c, &bst, c->rdf_block_start.size()));
-        HIPCHK(c, hipMemcpyAsync(brep, c->rdf_block_rep.data(), 4 * c->rdf_block_rep.size(), hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(bst, c->rdf_block_start.data(), 4 * c->rdf_block_start.size(), hipMemcpyHostToDevice, c->stream));
-        c->d.rdf_block_rep = brep;
-        c->d.rdf_block_start = bst;
-        TRY(dalloc(c, &c->d.origin, 16 * 3 * (size_t)P.n_total));
+        HIPCHK(c, hipMemcpyAsync((void *)c->d.rdf_block_rep, c->rdf_block_rep.data(), 4 * c->rdf_block_rep.size(),
+                                 hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync((void *)c->d.rdf_block_start, c->rdf_block_start.data(),
+                                 4 * c->rdf_block_start.size(), hipMemcpyHostToDevice, c->stream));
         const int64_t nt = P.n_total;
         if (cfg->init_mode == KAMD_INIT_GIVEN) {
             const double *a[9] = {st->x, st->y, st->z, st->vx, st->vy, st->vz, nullptr, nullptr, nullptr};
@@ -866,19 +1089,17 @@ extern "C" int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replic
                     for (int q = t; q < n_rep; q += nthr) place(q);
                 });
             for (auto &th : pool) th.join();
-            double *tmp;
-            TRY(dalloc(c, &tmp, 3 * (size_t)nt));
+            double *tmp = c->state_tmp;  // caller-order staging, 9 n_total doubles
             HIPCHK(c, hipMemcpyAsync(tmp, hx.data(), 8 * nt, hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(tmp + nt, hy.data(), 8 * nt, hipMemcpyHostToDevice, c->stream));
             HIPCHK(c, hipMemcpyAsync(tmp + 2 * nt, hz.data(), 8 * nt, hipMemcpyHostToDevice, c->stream));
             const double *a[9] = {tmp, tmp + nt, tmp + 2 * nt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
             HIPCHK(c, launch_import(c->d, a, nullptr, c->stream));
             HIPCHK(c, hipStreamSynchronize(c->stream));
-            dfree(c, tmp);
             TRY(mb_reassign(c, false, 0u));
         }
         TRY(force_rebuild_all(c));
-        TRY(forces(c, false));
+        TRY(heal_forces(c, false));
         TRY(do_export(c));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         return KAMD_OK;
@@ -896,8 +1117,7 @@ extern "C" int md_build_cells(kamd_ctx *c)
 {
     if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
     TRY(force_rebuild_all(c));
-    TRY(rebuild_chain(c, c->d));
-    return KAMD_OK;
+    return heal_build(c, false, false);
 }
 
 extern "C" int md_forces(kamd_ctx *c, uint32_t flags, double *obs_dev)
@@ -905,7 +1125,7 @@ extern "C" int md_forces(kamd_ctx *c, uint32_t flags, double *obs_dev)
     if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
     const bool energy = (flags & (KAMD_F_ENERGY | KAMD_F_VIRIAL)) != 0;
     if (energy && !obs_dev) return fail(c, KAMD_EINVAL, "energy/virial requested without obs_dev");
-    TRY(forces(c, energy));
+    TRY(heal_forces(c, energy));
     if (energy) {
         HIPCHK(c, launch_rep_reduce(c->d, 6, c->stream));
         HIPCHK(c, launch_store_pe_w(c->d, obs_dev, c->stream));
@@ -918,7 +1138,7 @@ extern "C" int md_step_nve(kamd_ctx *c, int32_t nsteps)
     if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
     if (nsteps < 0) return fail(c, KAMD_EINVAL, "nsteps < 0");
     if (nsteps == 0) return KAMD_OK;
-    TRY(enqueue_steps(c, nsteps, 0, 0, 0, false));
+    TRY(heal_steps(c, nsteps, 0, 0, 0));
     c->step += nsteps;
     return maybe_export(c);
 }
@@ -936,7 +1156,7 @@ extern "C" int md_step_nvt(kamd_ctx *c, int32_t nsteps, int32_t mode, int32_t n_
         return fail(c, KAMD_EINVAL, "bad thermostat mode %d", mode);
     }
     if (nsteps == 0) return KAMD_OK;
-    TRY(enqueue_steps(c, nsteps, 1, mode, n_reassign, false));
+    TRY(heal_steps(c, nsteps, 1, mode, n_reassign));
     c->step += nsteps;
     return maybe_export(c);
 }
@@ -972,58 +1192,25 @@ extern "C" int md_scale_velocities(kamd_ctx *c, const double *factor)
 extern "C" int md_rdf(kamd_ctx *c, double dr, int32_t n_bins, uint64_t *hist_dev)
 {
     if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
-    if (!(dr > 0.0) || n_bins <= 0 || !hist_dev) return fail(c, KAMD_EINVAL, "bad RDF arguments");
+    if (!(dr > 0.0) || !std::isfinite(dr) || n_bins <= 0 || !hist_dev) return fail(c, KAMD_EINVAL, "bad RDF arguments");
     if (3 * (size_t)n_bins * 4 > 60 * 1024) return fail(c, KAMD_EINVAL, "n_bins too large (max 5120)");
     const double rmax = n_bins * dr;
-    int64_t cells = 0;
     for (size_t r = 0; r < c->reps.size(); ++r) {
         const double L = c->reps[r].box;
-        if (rmax > 0.5 * L * (1.0 + 1e-12)) return fail(c, KAMD_EINVAL, "n_bins*dr = %.9g exceeds L/2 = %.9g (replica %zu)", rmax, 0.5 * L, r);
-        const bool planar = dim_of(&c->cfg) == 2;
-        // Cells as wide as the histogram range (a 3-cell stencil per axis), or
-        // half as wide (5 cells, the far ones skipped per particle) where they
-        // still hold several particles: fewer candidates, but more cells.
-        const int dim = dim_of(&c->cfg);
-        const double half_range_cell = c->reps[r].n / std::pow(L, dim) * std::pow(0.5 * rmax, dim);
-        const double per_range = half_range_cell >= 6.0 ? 2.0 : 1.0;
-        const int nc = (int)std::max(1.0, std::min(std::floor(per_range * L / rmax), (double)cell_cap(dim)));
-        const int ncell = planar ? nc * nc : nc * nc * nc;
-        c->rinfo[r].rdf_nc = nc;
-        c->rinfo[r].rdf_cell0 = (int32_t)std::min<int64_t>(cells, INT32_MAX);
-        c->rinfo[r].rdf_ncell = ncell;
-        cells += ncell;
+        if (rmax > 0.5 * L * (1.0 + 1e-12))
+            return fail(c, KAMD_EINVAL, "n_bins*dr = %.9g exceeds L/2 = %.9g (replica %zu)", rmax, 0.5 * L, r);
     }
-    if (cells > MAX_PLAN_CELLS)
-        return fail(c, KAMD_EINVAL, "RDF cell grid of %lld cells exceeds the limit of %lld (larger n_bins*dr)",
-                    (long long)cells, (long long)MAX_PLAN_CELLS);
-    Dev &d = c->d;
-    if (cells > c->rdf_cells_cap) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        dfree(c, d.rdf_count);
-        dfree(c, d.rdf_start);
-        TRY(dalloc(c, &d.rdf_count, cells));
-        TRY(dalloc(c, &d.rdf_start, cells));
-        c->rdf_cells_cap = cells;
-        if (!d.rdf_cell_of) {
-            TRY(dalloc(c, &d.rdf_cell_of, d.npad_total));
-            TRY(dalloc(c, &d.rdf_rank, d.npad_total));
-            TRY(dalloc(c, &d.rdf_pos, d.n_total));
-        }
-        drop_graph(c);
-    }
-    HIPCHK(c, hipMemcpyAsync((void *)d.rep, c->rinfo.data(), sizeof(RepInfo) * c->rinfo.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, launch_zero_i32(d.rdf_count, cells, c->stream));
-    HIPCHK(c, launch_rdf_prepare(d, c->stream));
-    HIPCHK(c, launch_rdf(d, dr, n_bins, (int)c->rdf_block_rep.size(), hist_dev, c->stream));
-    // the RepInfo copy must stay alive until the copy has been consumed
-    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the grid of each replica is chosen on the device, inside the capacity
+    // the workspace holds, so nothing here waits or allocates
+    HIPCHK(c, launch_rdf_prepare(c->d, rmax, c->stream));
+    HIPCHK(c, launch_rdf(c->d, dr, n_bins, (int)c->rdf_block_rep.size(), hist_dev, c->stream));
     return KAMD_OK;
 }
 
 extern "C" int md_msd(kamd_ctx *c, int32_t op, int32_t slot, double *out_dev)
 {
     if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
-    if (slot < 0 || slot >= 16) return fail(c, KAMD_EINVAL, "origin slot must be in [0, 16)");
+    if (slot < 0 || slot >= c->d.msd_slots) return fail(c, KAMD_EINVAL, "origin slot must be in [0, %d)", c->d.msd_slots);
     if (op == 0) {
         HIPCHK(c, launch_msd_set(c->d, slot, c->stream));
     } else if (op == 1) {
@@ -1040,7 +1227,7 @@ extern "C" int md_msd(kamd_ctx *c, int32_t op, int32_t slot, double *out_dev)
 extern "C" int md_van_hove(kamd_ctx *c, int32_t slot, double dr, int32_t n_bins, uint64_t *hist_dev)
 {
     if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
-    if (slot < 0 || slot >= 16) return fail(c, KAMD_EINVAL, "origin slot must be in [0, 16)");
+    if (slot < 0 || slot >= c->d.msd_slots) return fail(c, KAMD_EINVAL, "origin slot must be in [0, %d)", c->d.msd_slots);
     if (!(dr >= 1e-6) || !std::isfinite(dr) || n_bins <= 0 || n_bins > VH_MAX_BINS || !hist_dev)
         return fail(c, KAMD_EINVAL, "bad van Hove arguments (dr >= 1e-6, 0 < n_bins <= %d)", VH_MAX_BINS);
     HIPCHK(c, launch_van_hove(c->d, slot, dr, n_bins, hist_dev, c->stream));
@@ -1087,7 +1274,7 @@ extern "C" int md_observables_now(kamd_ctx *c, double *host_out)
     std::vector<double> ke(4 * nr), pw(4 * nr);
     HIPCHK(c, hipMemcpyAsync(ke.data(), c->obs_stage, 32 * nr, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    TRY(forces(c, true));
+    TRY(heal_forces(c, true));
     HIPCHK(c, launch_rep_reduce(c->d, 6, c->stream));
     HIPCHK(c, launch_store_obs(c->d, c->obs_stage, c->stream));
     HIPCHK(c, hipMemcpyAsync(pw.data(), c->obs_stage, 32 * nr, hipMemcpyDeviceToHost, c->stream));
@@ -1135,7 +1322,7 @@ extern "C" int md_import(kamd_ctx *c)
     const double *a[9] = {c->st.x, c->st.y, c->st.z, c->st.vx, c->st.vy, c->st.vz, nullptr, nullptr, nullptr};
     HIPCHK(c, launch_import(c->d, a, c->st.img, c->stream));
     TRY(force_rebuild_all(c));
-    TRY(forces(c, false));
+    TRY(heal_forces(c, false));
     return maybe_export(c);
 }
 
@@ -1192,6 +1379,41 @@ extern "C" int md_set_list_params(kamd_ctx *c, double skin, int32_t cell_div)
     return apply_list_params(c, skin, cell_div, false);
 }
 
+extern "C" int md_workspace_needed(kamd_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return fail(c, KAMD_EINVAL, "null argument");
+    Plan P;
+    make_plan(&c->cfg, c->reps.data(), (int)c->reps.size(), c->skin, c->cell_div, P, c->rows_floor);
+    *bytes = std::max(c->need_bytes, need_for(c, P));
+    return KAMD_OK;
+}
+
+extern "C" int md_set_workspace(kamd_ctx *c, void *workspace, size_t ws_bytes)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (!workspace || (uintptr_t)workspace % 256) return fail(c, KAMD_EINVAL, "workspace must be non-null and 256-byte aligned");
+    if ((char *)workspace == c->ws) return fail(c, KAMD_EINVAL, "that is the current workspace");
+    const size_t cur = need_for(c, c->plan);
+    if (ws_bytes < cur) {
+        c->need_bytes = std::max(c->need_bytes, cur);
+        return fail(c, KAMD_ENOMEM, "workspace of %zu bytes is too small: %zu needed", ws_bytes, cur);
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the fixed part, the cells and the lists move as they are
+    HIPCHK(c, hipMemcpyAsync(workspace, c->ws, cur, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->ws_owned) (void)hipFree(c->ws);
+    c->ws = (char *)workspace;
+    c->ws_bytes = ws_bytes;
+    c->ws_owned = false;
+    drop_graph(c);
+    bind_workspace(c, c->plan);
+    // a list that grew since (a healed overflow) takes its rows now
+    if (c->plan.rows < c->rows_floor) TRY(apply_list_params(c, c->skin, c->cell_div, false));
+    if (c->need_bytes <= c->ws_bytes) c->need_bytes = 0;
+    return KAMD_OK;
+}
+
 extern "C" int md_stats(kamd_ctx *c, double *host_out)
 {
     if (!c || !host_out) return fail(c, KAMD_EINVAL, "null argument");
@@ -1238,22 +1460,12 @@ static size_t blob_size(const kamd_ctx *c)
     return sizeof(BlobHeader) + 9 * 8 * nt + 3 * 4 * nt + sizeof(RepDyn) * c->reps.size();
 }
 
-static int ensure_tmp(kamd_ctx *c)
-{
-    if (!c->state_tmp) {
-        TRY(dalloc(c, &c->state_tmp, 9 * (size_t)c->d.n_total));
-        TRY(dalloc(c, &c->img_tmp, 3 * (size_t)c->d.n_total));
-    }
-    return KAMD_OK;
-}
-
 extern "C" int md_get_state(kamd_ctx *c, void *blob, size_t *bytes)
 {
     if (!c || !bytes) return fail(c, KAMD_EINVAL, "null argument");
     const size_t need = blob_size(c);
     if (!blob) { *bytes = need; return KAMD_OK; }
     if (*bytes < need) return fail(c, KAMD_EINVAL, "blob too small (%zu < %zu)", *bytes, need);
-    TRY(ensure_tmp(c));
     const size_t nt = c->d.n_total;
     double *a[9];
     for (int k = 0; k < 9; ++k) a[k] = c->state_tmp + k * nt;
@@ -1280,7 +1492,6 @@ extern "C" int md_set_state(kamd_ctx *c, const void *blob, size_t bytes)
     std::memcpy(&h, blob, sizeof h);
     if (h.magic != BLOB_MAGIC || h.n_total != c->d.n_total || h.n_rep != (int64_t)c->reps.size())
         return fail(c, KAMD_EINVAL, "blob does not match this context");
-    TRY(ensure_tmp(c));
     const size_t nt = c->d.n_total;
     const char *p = (const char *)blob + sizeof h;
     HIPCHK(c, hipMemcpyAsync(c->state_tmp, p, 9 * 8 * nt, hipMemcpyHostToDevice, c->stream));
@@ -1296,7 +1507,7 @@ extern "C" int md_set_state(kamd_ctx *c, const void *blob, size_t bytes)
     HIPCHK(c, hipMemcpyAsync(c->d.counters + 1, &host_step, 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     TRY(force_rebuild_all(c));
-    TRY(rebuild_chain(c, c->d));
+    TRY(heal_build(c, false, false));
     return maybe_export(c);
 }
 
@@ -1339,6 +1550,15 @@ extern "C" int md_autotune(kamd_ctx *c, int32_t probe_steps, double *host_out)
     std::vector<double> skins;
     for (double s : {0.2, 0.25, 0.3, 0.35, 0.4, 0.5})
         if (c->rc_max + s < 0.5 * Lmin || s <= 0.2) skins.push_back(s);
+    // every candidate must fit the workspace before any is tried
+    size_t need = 0;
+    for (double s : skins)
+        for (int dv = 1; dv <= 2; ++dv) {
+            Plan P;
+            make_plan(&c->cfg, c->reps.data(), (int)c->reps.size(), s, dv, P, c->rows_floor);
+            if (P.ncells_wide <= MAX_PLAN_CELLS) need = std::max(need, need_for(c, P));
+        }
+    TRY(grow_workspace(c, need));
     struct Probe {
         double skin;
         int div;
@@ -1353,6 +1573,9 @@ extern "C" int md_autotune(kamd_ctx *c, int32_t probe_steps, double *host_out)
     int rc = KAMD_OK;
     for (double s : skins) {
         for (int dv = 1; dv <= 2 && !rc; ++dv) {
+            Plan Pt;
+            make_plan(&c->cfg, c->reps.data(), (int)c->reps.size(), s, dv, Pt, c->rows_floor);
+            if (Pt.ncells_wide > MAX_PLAN_CELLS) continue;
             rc = apply_list_params(c, s, dv, false);
             if (!rc) rc = md_set_state(c, blob.data(), nb);
             if (!rc) rc = enqueue_steps(c, std::max(1, probe_steps / 4), 0, 0, 0, false);  // warm-up
@@ -1366,7 +1589,12 @@ extern "C" int md_autotune(kamd_ctx *c, int32_t probe_steps, double *host_out)
             (void)hipEventElapsedTime(&ms, e0, e1);
             uint32_t word = 0;
             (void)hipMemcpy(&word, c->d.err, 4, hipMemcpyDeviceToHost);
-            if (word == 0) probes.push_back({s, dv, (double)ms / probe_steps});
+            if (word == 0) {
+                probes.push_back({s, dv, (double)ms / probe_steps});
+            } else if (word == KAMD_DEV_LIST_OVERFLOW) {  // this candidate's list is too short: skip it
+                const uint32_t zero = 0;
+                (void)hipMemcpy(c->d.err, &zero, 4, hipMemcpyHostToDevice);
+            }
         }
         if (rc) break;
     }
@@ -1511,8 +1739,8 @@ extern "C" int md_destroy(kamd_ctx *c)
     if (!c) return KAMD_OK;
     (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
-    for (void *p : c->allocs) (void)hipFree(p);
-    c->allocs.clear();
+    if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+    c->ws = nullptr;
     delete c;
     return KAMD_OK;
 }

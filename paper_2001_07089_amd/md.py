@@ -35,7 +35,7 @@ EXPORTED = ("md_workspace_size", "md_admit", "md_init", "md_build_cells", "md_fo
             "md_import", "md_graph_capture", "md_graph_launch", "md_autotune", "md_set_list_params",
             "md_stats", "md_get_state", "md_set_state", "md_profile", "md_status", "md_last_error", "md_destroy",
             "md_log_schedule", "md_set_temperature", "md_scale_velocities", "md_van_hove",
-            "md_observables_now", "md_clear_samples")
+            "md_observables_now", "md_clear_samples", "md_workspace_needed", "md_set_workspace")
 
 
 class KamdError(RuntimeError):
@@ -61,7 +61,8 @@ class Config(C.Structure):
     _fields_ = [("model", Model), ("precision", C.c_int32), ("dt", C.c_double), ("skin", C.c_double),
                 ("init_mode", C.c_int32), ("min_dist", C.c_double), ("cell_div", C.c_int32),
                 ("list_capacity", C.c_double), ("auto_sync", C.c_int32), ("dim", C.c_int32),
-                ("pe_unshifted", C.c_int32), ("sample_every", C.c_int32), ("sample_capacity", C.c_int32)]
+                ("pe_unshifted", C.c_int32), ("sample_every", C.c_int32), ("sample_capacity", C.c_int32),
+                ("msd_slots", C.c_int32)]
 
 
 _lib = None
@@ -79,7 +80,9 @@ def lib():
         sig = {
             "md_workspace_size": [C.POINTER(Config), P, i32, C.POINTER(C.c_size_t)],
             "md_admit": [C.POINTER(Config), P, i32, C.c_size_t, P, C.POINTER(i32)],
-            "md_init": [C.POINTER(P), C.POINTER(Config), P, i32, C.POINTER(State), P],
+            "md_init": [C.POINTER(P), C.POINTER(Config), P, i32, C.POINTER(State), P, C.c_size_t, P],
+            "md_workspace_needed": [P, C.POINTER(C.c_size_t)],
+            "md_set_workspace": [P, P, C.c_size_t],
             "md_build_cells": [P],
             "md_forces": [P, u32, P],
             "md_step_nve": [P, i32],
@@ -135,7 +138,7 @@ def make_model(eps=KA_EPS, sigma=KA_SIGMA, rc_factor=KA_RC_FACTOR) -> Model:
 
 def make_config(precision="fp64", dt=0.005, skin=0.3, init_mode=INIT_GIVEN, min_dist=0.8, cell_div=1,
                 list_capacity=0.0, auto_sync=1, model=None, dim=3, pe_unshifted=False, sample_every=0,
-                sample_capacity=0) -> Config:
+                sample_capacity=0, msd_slots=0) -> Config:
     c = Config()
     c.model = model if model is not None else make_model()
     c.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
@@ -150,6 +153,7 @@ def make_config(precision="fp64", dt=0.005, skin=0.3, init_mode=INIT_GIVEN, min_
     c.pe_unshifted = 1 if pe_unshifted else 0
     c.sample_every = int(sample_every)
     c.sample_capacity = int(sample_capacity)
+    c.msd_slots = int(msd_slots)
     return c
 
 
@@ -188,11 +192,23 @@ def md_admit(cfg: Config, reps, budget_bytes: int):
     return adm, cnt.value
 
 
-def md_init(cfg: Config, reps, state: State, stream: int):
+def md_init(cfg: Config, reps, state: State, stream: int, workspace: int = 0, ws_bytes: int = 0):
+    """workspace: device address of ws_bytes caller-owned bytes, or 0 for a
+    library-allocated workspace."""
     ctx = C.c_void_p()
     _check(lib().md_init(C.byref(ctx), C.byref(cfg), C.cast(reps, C.c_void_p), len(reps), C.byref(state),
-                         C.c_void_p(stream)))
+                         C.c_void_p(workspace or None), int(ws_bytes), C.c_void_p(stream)))
     return ctx
+
+
+def md_workspace_needed(ctx) -> int:
+    b = C.c_size_t()
+    _check(lib().md_workspace_needed(ctx, C.byref(b)), ctx)
+    return b.value
+
+
+def md_set_workspace(ctx, workspace: int, ws_bytes: int):
+    _check(lib().md_set_workspace(ctx, C.c_void_p(workspace), int(ws_bytes)), ctx)
 
 
 def md_build_cells(ctx):
@@ -336,13 +352,16 @@ class System:
     """Replicas of the Kob-Andersen mixture on the current GPU.
 
     Owns caller-order torch tensors x..az (float64) and img (int32, 3 x n) on
-    ``cuda``; the library's own buffers live inside the context.
+    ``cuda``, and the context's device workspace as a torch uint8 tensor of
+    md_workspace_size bytes, which it replaces by a larger one when a call
+    reports KAMD_ENOMEM (a longer list after a skin change, an autotuner
+    candidate or a healed list overflow) and then repeats the call.
     """
 
     def __init__(self, replicas, precision="fp64", dt=0.005, skin=0.3, init="given",
                  positions=None, velocities=None, min_dist=0.8, cell_div=1, list_capacity=0.0,
                  auto_sync=True, model=None, device="cuda", dim=3, pe_unshifted=False, sample_every=0,
-                 sample_capacity=0):
+                 sample_capacity=0, msd_slots=0):
         import torch
         self.torch = torch
         self.reps = make_replicas(replicas)
@@ -351,7 +370,8 @@ class System:
         self.offsets = [r.offset for r in self.reps]
         mode = {"given": INIT_GIVEN, "rsa": INIT_RSA, "lattice": INIT_LATTICE}[init]
         self.cfg = make_config(precision, dt, skin, mode, min_dist, cell_div, list_capacity,
-                               1 if auto_sync else 0, model, dim, pe_unshifted, sample_every, sample_capacity)
+                               1 if auto_sync else 0, model, dim, pe_unshifted, sample_every, sample_capacity,
+                               msd_slots)
         n = self.n_total
         # a dedicated stream: graph capture is not allowed on the legacy null
         # stream, and every allocation below is ordered on it
@@ -371,8 +391,31 @@ class System:
             setattr(st, k, v.data_ptr())
         st.img = self.img.data_ptr()
         self.state = st
+        self.device = device
+        self.ws_bytes = md_workspace_size(self.cfg, self.reps)
+        with torch.cuda.stream(self.stream):
+            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.stream.synchronize()
-        self.ctx = md_init(self.cfg, self.reps, st, self.stream.cuda_stream)
+        self.ctx = None
+        self.ctx = md_init(self.cfg, self.reps, st, self.stream.cuda_stream, self.ws.data_ptr(), self.ws_bytes)
+
+    def grow_workspace(self):
+        """Move the context into a workspace of md_workspace_needed bytes."""
+        need = md_workspace_needed(self.ctx)
+        with self.torch.cuda.stream(self.stream):
+            ws = self.torch.empty(need, dtype=self.torch.uint8, device=self.device)
+        md_set_workspace(self.ctx, ws.data_ptr(), need)
+        self.ws, self.ws_bytes = ws, need
+
+    def call(self, fn, *args):
+        """fn(ctx, *args), repeated once in a larger workspace after KAMD_ENOMEM."""
+        try:
+            return fn(self.ctx, *args)
+        except KamdError as e:
+            if e.code != KAMD_ENOMEM:
+                raise
+            self.grow_workspace()
+            return fn(self.ctx, *args)
 
     def _zeros(self, shape, dtype):
         with self.torch.cuda.stream(self.stream):
@@ -386,16 +429,31 @@ class System:
     def forces(self, energy=False):
         if energy:
             obs = self._zeros((self.n_rep, 2), self.torch.float64)
-            md_forces(self.ctx, F_FORCE | F_ENERGY | F_VIRIAL, obs.data_ptr())
+            self.call(md_forces, F_FORCE | F_ENERGY | F_VIRIAL, obs.data_ptr())
             return self._host(obs)
-        md_forces(self.ctx, F_FORCE)
+        self.call(md_forces, F_FORCE)
         return None
 
     def step_nve(self, n):
-        md_step_nve(self.ctx, n)
+        self.call(md_step_nve, n)
 
     def step_nvt(self, n, mode=NVT_STOCHASTIC, n_reassign=50, tau=0.5):
-        md_step_nvt(self.ctx, n, mode, n_reassign, tau)
+        self.call(md_step_nvt, n, mode, n_reassign, tau)
+
+    def build_cells(self):
+        self.call(md_build_cells)
+
+    def set_list_params(self, skin, cell_div=1):
+        self.call(md_set_list_params, skin, cell_div)
+
+    def autotune(self, probe_steps=100):
+        return self.call(md_autotune, probe_steps)
+
+    def capture(self, nsteps, ensemble=0, mode=NVT_STOCHASTIC, n_reassign=50, tau=0.5):
+        md_graph_capture(self.ctx, nsteps, ensemble, mode, n_reassign, tau)
+
+    def launch(self):
+        md_graph_launch(self.ctx)
 
     def rdf(self, dr, n_bins, hist=None):
         if hist is None:
