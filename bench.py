@@ -221,7 +221,7 @@ def batched(md, torch, W, steps):
     log(f"batch init (rsa, {len(reps)} replicas, {wl.n_total} particles) {time.perf_counter() - t0:.1f} s")
     s.step_nvt(500, md.NVT_STOCHASTIC, n_reassign=10)
     s.step_nvt(1500, md.NVT_STOCHASTIC, n_reassign=50)
-    tune = md.md_autotune(s.ctx, 60)
+    tune = s.autotune(60)
     s.step_nve(200)
     s.stream.synchronize()
     md.md_graph_capture(s.ctx, steps, 0)
@@ -307,7 +307,7 @@ def planar_leg(md, torch, W, steps=1000):
     s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision="mixed_fixed", dt=wl.dt, skin=0.3,
                   init="lattice", auto_sync=False, dim=2)
     s.step_nvt(12000, md.NVT_STOCHASTIC, n_reassign=10)
-    tune = md.md_autotune(s.ctx, 100)
+    tune = s.autotune(100)
     s.step_nve(200)
     el, e0, e1 = timed_graph(s, md, torch, steps)
     out = {"workload": wl.name, "n_atoms": r.n, "box": r.box, "value": r.n * steps / el, "unit": "atom-steps/s",
@@ -382,10 +382,10 @@ def main():
     equilibrate(s, md, first)
     tune = None
     if a.skin is not None:
-        md.md_set_list_params(s.ctx, a.skin, a.cell_div)
+        s.set_list_params(a.skin, a.cell_div)
         log(f"list parameters fixed: skin {a.skin}, cell_div {a.cell_div}")
     elif not a.no_autotune:
-        tune = md.md_autotune(s.ctx, 100)
+        tune = s.autotune(100)
         log(f"autotune: {tune}")
     if a.equil > first:
         s.step_nvt(a.equil - first, md.NVT_STOCHASTIC, n_reassign=50)
@@ -430,7 +430,7 @@ def main():
     if not a.no_fp64 and a.precision != "fp64":
         s2, _ = make_system(wl, "fp64", md)
         equilibrate(s2, md, a.equil)
-        md.md_set_list_params(s2.ctx, skin, int(st["cell_div"]))
+        s2.set_list_params(skin, int(st["cell_div"]))
         s2.step_nve(a.warmup)
         k2 = max(100, a.steps // 2)
         el2, f0, f1 = timed_graph(s2, md, torch, k2)

@@ -361,7 +361,7 @@ class System:
     def __init__(self, replicas, precision="fp64", dt=0.005, skin=0.3, init="given",
                  positions=None, velocities=None, min_dist=0.8, cell_div=1, list_capacity=0.0,
                  auto_sync=True, model=None, device="cuda", dim=3, pe_unshifted=False, sample_every=0,
-                 sample_capacity=0, msd_slots=0):
+                 sample_capacity=0, msd_slots=0, own_workspace=True):
         import torch
         self.torch = torch
         self.reps = make_replicas(replicas)
@@ -392,12 +392,20 @@ class System:
         st.img = self.img.data_ptr()
         self.state = st
         self.device = device
-        self.ws_bytes = md_workspace_size(self.cfg, self.reps)
-        with torch.cuda.stream(self.stream):
-            self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        # room for the list at no less than the default capacity, so that a
+        # list that outgrows a smaller list_capacity heals in place
+        roomy = make_config(precision, dt, skin, mode, min_dist, cell_div, max(list_capacity, 1.6),
+                            1, model, dim, pe_unshifted, sample_every, sample_capacity, msd_slots)
+        self.ws_bytes = max(md_workspace_size(self.cfg, self.reps), md_workspace_size(roomy, self.reps))
+        self.ws = None
+        if own_workspace:
+            with torch.cuda.stream(self.stream):
+                self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
         self.stream.synchronize()
         self.ctx = None
-        self.ctx = md_init(self.cfg, self.reps, st, self.stream.cuda_stream, self.ws.data_ptr(), self.ws_bytes)
+        # own_workspace False: the library allocates (and grows) its own
+        self.ctx = md_init(self.cfg, self.reps, st, self.stream.cuda_stream,
+                           self.ws.data_ptr() if own_workspace else 0, self.ws_bytes if own_workspace else 0)
 
     def grow_workspace(self):
         """Move the context into a workspace of md_workspace_needed bytes."""

@@ -80,10 +80,10 @@ def tune(system, probe_steps: int = 100, path: str = None, device: str = None, r
     key = workload_key(device, system.cfg.precision, system.reps)
     hit = None if refresh else load(path).get(key)
     if hit and "skin" in hit and "cell_div" in hit:
-        md.md_set_list_params(system.ctx, float(hit["skin"]), int(hit["cell_div"]))
+        system.set_list_params(float(hit["skin"]), int(hit["cell_div"]))
         return {"skin": float(hit["skin"]), "cell_div": int(hit["cell_div"]),
                 "ms_per_step": hit.get("ms_per_step"), "cached": True, "key": key}
-    res = md.md_autotune(system.ctx, probe_steps)
+    res = system.autotune(probe_steps)
     store(path, key, {"skin": res["skin"], "cell_div": res["cell_div"], "ms_per_step": res["ms_per_step"],
                       "probe_steps": int(probe_steps)})
     return dict(res, cached=False, key=key)

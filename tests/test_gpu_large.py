@@ -94,7 +94,7 @@ def test_large_planar_bath_and_autotune_match_oracle():
         assert err <= 1e-5
 
     check()
-    tune = md.md_autotune(s.ctx, 20)
+    tune = s.autotune(20)
     log(f"  autotune {tune}")
     s.step_nvt(100, md.NVT_STOCHASTIC, n_reassign=10)
     assert s.status() == 0

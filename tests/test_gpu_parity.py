@@ -417,7 +417,7 @@ def test_autotune_picks_a_valid_skin():
     log("case autotune")
     s = system([(4000, 0.8, 24, 1.2)], "mixed")
     x0 = s.numpy()["x"].copy()
-    res = md.md_autotune(s.ctx, 20)
+    res = s.autotune(20)
     assert 0.2 <= res["skin"] <= 0.5 and res["cell_div"] in (1, 2) and res["ms_per_step"] > 0
     s.sync()
     assert np.array_equal(s.numpy()["x"], x0)  # state restored

@@ -11,8 +11,13 @@ from paper_2001_07089_amd import workload as W
 
 
 def _system(reps, precision="mixed_fixed"):
+    """Stands in for md.System: its autotune / set_list_params call the
+    library functions, which the fixture replaces."""
     cfg = md.make_config(precision)
-    return types.SimpleNamespace(ctx="CTX", cfg=cfg, reps=md.make_replicas(reps))
+    s = types.SimpleNamespace(ctx="CTX", cfg=cfg, reps=md.make_replicas(reps))
+    s.autotune = lambda probe_steps=100: md.md_autotune(s.ctx, probe_steps)
+    s.set_list_params = lambda skin, cell_div=1: md.md_set_list_params(s.ctx, skin, cell_div)
+    return s
 
 
 @pytest.fixture
