@@ -98,12 +98,19 @@ def lib():
         L.ora_log_schedule.restype = C.c_int
         L.ora_num_threads.argtypes = []
         L.ora_num_threads.restype = C.c_int
+        L.ora_set_num_threads.argtypes = [C.c_int]
+        L.ora_set_num_threads.restype = None
         _LIB = L
     return _LIB
 
 
 def num_threads() -> int:
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (n < 1: all processors)."""
+    lib().ora_set_num_threads(int(n))
 
 
 def _c(a, dtype=np.float64):

@@ -609,3 +609,14 @@ int ora_num_threads(void)
     return 1;
 #endif
 }
+
+/* Set the threads of the OpenMP loops (for timing the oracle on 1 core and
+ * on all cores); n < 1 restores the number of processors. */
+void ora_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n >= 1 ? n : omp_get_num_procs());
+#else
+    (void)n;
+#endif
+}

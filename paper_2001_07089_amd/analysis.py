@@ -94,3 +94,29 @@ def write_lammps_rdf(f, blocks, fix_id: str = "myrdf", compute_id: str = "rdfAAB
         f.write(f"{int(step)} {t.shape[0]}\n")
         for row in t:
             f.write(f"{int(row[0])} " + " ".join(f"{v:.10g}" for v in row[1:]) + "\n")
+
+
+def energy_drift(rows, window_steps: int = 500):
+    """NVE energy drift from sampled rows {step, KE, PE, E_tot, T, W} of one
+    replica (md_observables), per 10^4 steps.
+
+    windowed: |<E>_last - <E>_first| / |<E>_first| with <E> the mean of E_tot
+    over the first and the last window_steps of the rows, scaled by 10^4 over
+    the distance between the two windows' starts; slope: the least-squares
+    slope of E_tot against the step, times 10^4, over |<E>|.  Also the drift
+    per particle is left to the caller (divide by N).  Returns a dict.
+    """
+    import numpy as np
+    rows = np.asarray(rows)
+    step, e = rows[:, 0], rows[:, 3]
+    if len(step) < 4:
+        return {"windowed": float("nan"), "slope": float("nan"), "steps": 0}
+    ds = step[1] - step[0]
+    first = e[step < step[0] + window_steps]
+    last = e[step > step[-1] - window_steps]
+    span = (step[-1] - step[0]) - window_steps + ds
+    windowed = abs(last.mean() - first.mean()) / abs(first.mean()) * (1e4 / span) if span > 0 else float("nan")
+    slope = np.polyfit(step, e, 1)[0]
+    return {"windowed": float(windowed), "slope": float(abs(slope) * 1e4 / abs(e.mean())),
+            "steps": int(step[-1] - step[0] + ds), "window_steps": int(window_steps),
+            "e_mean": float(e.mean())}

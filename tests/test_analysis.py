@@ -32,3 +32,18 @@ def test_van_hove_normalisation_integrates_to_one():
         assert np.allclose((G * size).sum(axis=1), 1.0, rtol=1e-12)
     assert analysis.shells(1, 1.0, 3)[1][0] == pytest.approx(4 * math.pi / 3)
     assert analysis.shells(1, 1.0, 2)[1][0] == pytest.approx(math.pi)
+
+
+def test_energy_drift_windowed_and_slope():
+    """A linear energy ramp of known slope: both definitions return it."""
+    import numpy as np
+    from paper_2001_07089_amd import analysis
+    steps = np.arange(10, 10001, 10, dtype=float)
+    e = -6000.0 * (1.0 + 2e-9 * steps)            # relative drift 2e-5 per 10^4 steps
+    rows = np.zeros((steps.size, 6))
+    rows[:, 0], rows[:, 3] = steps, e
+    out = analysis.energy_drift(rows, 500)
+    assert abs(out["windowed"] - 2e-5) < 1e-7
+    assert abs(out["slope"] - 2e-5) < 1e-7
+    rows[:, 3] = -6000.0 + 0.01 * np.sin(steps)   # fluctuation only: no drift
+    assert analysis.energy_drift(rows, 500)["slope"] < 1e-6

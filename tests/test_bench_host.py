@@ -1,6 +1,6 @@
-"""Host-side logic of bench.py (no GPU): the one-GPU guard, the algorithmic
-byte count of the roofline, and the rule that a stored HBM traffic figure is
-reported only for the kernel source and list parameters it was measured on."""
+"""Host-side logic of bench.py (no GPU): the one-GPU guard, the roofline
+pricing, and the rule that a stored HBM traffic figure is reported only for
+the kernel source and list parameters it was measured on."""
 import os
 import subprocess
 import sys
@@ -20,9 +20,21 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.stdout == ""
 
 
-def test_algorithmic_bytes_are_list_plus_state_per_particle():
-    assert bench.algorithmic_bytes(270.0, 4, "mixed_fixed") == 4 * (270.0 + 168)
-    assert bench.algorithmic_bytes(270.0, 4, "fp64") == 4 * (270.0 + 48)
+def test_roofline_prices_useful_pair_flops_against_the_fp32_peak():
+    """achieved = ordered in-cutoff pairs x 19 FLOP / mean launch time, over
+    157.3 TFLOP/s; issued work counts the list candidates; the HBM view
+    counts 150 bytes per atom-step."""
+    prof = {"force_ms": 0.25, "pairs": 67216584.0}
+    stats = {"mean_list_len": 104.0, "skin": 0.4, "cell_div": 1.0}
+    n = 1 << 20
+    r = bench.roofline(prof, stats, n, "mixed_fixed")
+    assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
+    assert r["achieved"] == pytest.approx(67216584.0 * 19 / 0.25e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
+    assert r["issued_tflops"] == pytest.approx(104.0 * n * 19 / 0.25e-3 / 1e12)
+    assert r["hbm_view"]["achieved_gbs"] == pytest.approx(n * 150 / 0.25e-3 / 1e9)
+    assert r["kernel"] == "k_force_mixed<true,false,true>"
+    assert bench.kernel_name("fp64") == "k_force_fp64<false,true>"
 
 
 def _record():

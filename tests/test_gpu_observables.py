@@ -14,6 +14,7 @@ import sys
 import numpy as np
 import pytest
 
+from paper_2001_07089_amd import analysis
 from paper_2001_07089_amd import md
 from paper_2001_07089_amd import workload as W
 
@@ -26,16 +27,8 @@ def log(*a):
 
 
 def windowed_drift(rows, window_steps=500):
-    """|<E>_last - <E>_first| / |<E>_first| per 10^4 steps, from rows of
-    {step, KE, PE, E, T, W} of one replica; also the linear-fit slope of E per
-    10^4 steps relative to |<E>|."""
-    step, e = rows[:, 0], rows[:, 3]
-    first = e[step < step[0] + window_steps]
-    last = e[step > step[-1] - window_steps]
-    span = (step[-1] - step[0]) - window_steps + (step[1] - step[0])
-    d = abs(last.mean() - first.mean()) / abs(first.mean()) * (1e4 / span)
-    slope = np.polyfit(step, e, 1)[0]
-    return d, abs(slope) * 1e4 / abs(e.mean())
+    out = analysis.energy_drift(rows, window_steps)
+    return out["windowed"], out["slope"]
 
 
 def test_rows_match_the_instant_observables():

@@ -368,11 +368,32 @@ def test_checkpoint_resume_is_bitwise_fixed():
         s.close()
 
 
-def test_list_overflow_sets_error_bit():
-    log("case list overflow")
-    s = system([(1000, 1.0, 22, 1.2)], "fp64", list_capacity=0.05)
+def test_list_overflow_heals_in_a_graph_replay_by_a_rebuild():
+    """Eager calls heal an overflowing list themselves (test_gpu_workspace);
+    a graph replay cannot: its steps run on a truncated list and the bit stays
+    for md_status.  md_build_cells then grows the list, after which forces
+    equal the oracle's again."""
+    log("case list overflow in a graph")
+    n = 1000
+    s = system([(n, 1.0, 22, 1.2)], "fp64", list_capacity=0.05)
+    assert s.status() == 0                                  # md_init healed its first build
+    rows0 = md.md_stats(s.ctx)["list_rows"]
+    # skin 1.0: list radius 3.5 instead of 2.8, about twice the partners, more
+    # than the rows the healed skin-0.3 list got (the capacity stays 0.05)
+    s.set_list_params(1.0, 1)
+    rows1 = md.md_stats(s.ctx)["list_rows"]
+    md.md_graph_capture(s.ctx, 20, 0)
+    md.md_graph_launch(s.ctx)                               # its first step rebuilds and overflows
     w = s.status()
+    log(f"  rows {rows0} -> {rows1}, word 0x{w:x}")
     assert w & md.DEV_LIST_OVERFLOW
+    s.build_cells()
+    assert s.status() == 0
+    assert md.md_stats(s.ctx)["list_rows"] > rows1
+    s.forces()
+    a = s.numpy()
+    fx, fy, fz, _, _ = O.forces(a["x"], a["y"], a["z"], W.n_a_for(n), W.box_for(n, 1.2), "brute")
+    assert normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz)) <= 1e-12
     s.close()
 
 
