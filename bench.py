@@ -63,6 +63,8 @@ def parse():
     p.add_argument("--skin", type=float, default=None, help="fixed list skin (skips the autotuner)")
     p.add_argument("--cell-div", type=int, default=1, help="cell division with --skin")
     p.add_argument("--drift-steps", type=int, default=10000, help="NVE steps of each drift measurement")
+    p.add_argument("--windows", action="store_true",
+                   help="mixed precisions: the step kernel gathers from LDS windows of the stencil rows")
     p.add_argument("--profile-steps", type=int, default=200)
     p.add_argument("--no-analysis", action="store_true", help="skip the RDF / MSD timings")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU run of the headline system")
@@ -346,8 +348,7 @@ def medium_leg(md, torch, W, nvt_steps=20000, nve_steps=10000):
                 c.stream.synchronize()
                 t_rdf += time.perf_counter() - t1
                 n_rdf += 1
-    g = analysis.rdf(c._host(hist)[0], rep.n, rep.n_a, rep.box, dr, n_rdf)
-    r = (np.arange(nb) + 0.5) * dr
+    r, g = analysis.rdf(c._host(hist)[0], rep.n, rep.n_a, rep.box, dr, n_rdf)
     ipk = int(np.argmax(g[0]))
     last = {k: v[-1] for k, v in msd.items()}
     out["analysis"] = {"rdf_samples": n_rdf, "rdf_ms_per_sample": t_rdf * 1e3 / max(n_rdf, 1),
@@ -595,6 +596,8 @@ def main():
 
     t0 = time.perf_counter()
     s = make_system(md, rep, a.precision, wl.dt, init, samples=a.drift_steps)
+    if a.windows:
+        md.md_set_force_kernel(s.ctx, 1)
     log(f"init ({init}) {time.perf_counter() - t0:.1f} s")
     # melt the start, tune the list on the liquid, then equilibrate at the
     # tuned list parameters (so nearly every launch of the run, and of a

@@ -81,9 +81,11 @@ enum {
 enum {
     KAMD_DEV_NONFINITE = 1u,     /* a position, velocity or force became inf/nan       */
     KAMD_DEV_LIST_OVERFLOW = 2u, /* a neighbour list exceeded its capacity            */
-    KAMD_DEV_FORCE_RANGE = 4u    /* MIXED_FIXED: a pair came so close that its force
+    KAMD_DEV_FORCE_RANGE = 4u,   /* MIXED_FIXED: a pair came so close that its force
                                     reached 2^25 (beyond it the 2^-26-unit rounding is
                                     no longer exact), or a net force exceeded 1e8     */
+    KAMD_DEV_LIST_FORMAT = 8u    /* internal: a force kernel met a list part stored in
+                                    a format it does not read, and skipped it          */
 };
 
 /* Pair model: epsilon and sigma per pair type in the order AA, AB, BB, and the
@@ -339,11 +341,22 @@ int md_autotune(kamd_ctx *ctx, int32_t probe_steps, double *host_out);
 /* Change skin and cell division (forces a rebuild at the next step). */
 int md_set_list_params(kamd_ctx *ctx, double skin, int32_t cell_div);
 
-/* Statistics: host_out (host, FP64 [9]) = {steps, rebuilds, n_total,
- * list_rows, mean_list_len, max_list_len, skin, cell_div, mean_list_bytes}.
- * List lengths count partners at the last build (without wavefront padding);
- * mean_list_bytes is their stored size per particle (4 bytes per 32-bit entry,
- * 2 per 16-bit entry).  Syncs. */
+/* Step-kernel variant.  windows (mixed precisions): 1 gathers
+ * the neighbours of a list part from an LDS copy of the wavefront's stencil
+ * rows when that copy fits (the list then stores 16-bit offsets into it), 0
+ * gathers every neighbour from global memory (the default); a change forces a
+ * rebuild at the next step.  wg_size: threads per block of the step kernel, 64, 128 or 256
+ * (0 keeps the current one; 256 by default).  The forces are the same either
+ * way (bit for bit with MIXED_FIXED).  Drops a captured graph.  KAMD_EINVAL
+ * for windows = 1 in FP64.  Syncs. */
+int md_set_force_kernel(kamd_ctx *ctx, int32_t windows, int32_t wg_size);
+
+/* Statistics: host_out (host, FP64 [12]) = {steps, rebuilds, n_total,
+ * list_rows, mean_list_len, max_list_len, skin, cell_div, mean_list_bytes,
+ * windows (the force-kernel variant), fraction of list parts gathered from a
+ * window, step-kernel threads per block}.  List lengths count partners at the last build (without
+ * wavefront padding); mean_list_bytes is their stored size per particle (4
+ * bytes per 32-bit entry, 2 per 16-bit entry).  Syncs. */
 int md_stats(kamd_ctx *ctx, double *host_out);
 
 /* Checkpoint: the full dynamical state (positions, velocities, forces, image

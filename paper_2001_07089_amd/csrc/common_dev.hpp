@@ -15,10 +15,11 @@ __device__ inline int xcd_block(int b, int nb)
     return x * q + min(x, r) + (b >> 3);
 }
 
+template <int WPB = WAVES_PER_BLOCK>
 __device__ inline int wave_id_remapped()
 {
     int b = xcd_block(blockIdx.x, gridDim.x);
-    return b * WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    return b * WPB + (threadIdx.x >> 6);
 }
 
 __device__ inline int lane_id() { return threadIdx.x & 63; }
@@ -122,12 +123,13 @@ __device__ inline void drift_one(const Dev &d, int s, int rep, double dt, double
 }
 
 // Per-replica maximum of the wavefront maxima of one block, one atomicMax per
-// replica present in the block (a block holds 4 consecutive wavefronts, which
-// may straddle two replicas).  All threads of the block must call it.
+// replica present in the block (a block holds WPB consecutive wavefronts,
+// which may straddle two replicas).  All threads of the block must call it.
+template <int WPB = WAVES_PER_BLOCK>
 __device__ inline void block_disp_max(uint32_t *maxdisp, bool valid, int rep, float d2)
 {
-    __shared__ float wmax[WAVES_PER_BLOCK];
-    __shared__ int wrep[WAVES_PER_BLOCK];
+    __shared__ float wmax[WPB];
+    __shared__ int wrep[WPB];
     d2 = wave_max(d2);
     const int wv = threadIdx.x >> 6;
     if (lane_id() == 0) {
@@ -145,7 +147,7 @@ __device__ inline void block_disp_max(uint32_t *maxdisp, bool valid, int rep, fl
         };
         int r = -1;
         float m = 0.0f;
-        for (int k = 0; k < WAVES_PER_BLOCK; ++k) {
+        for (int k = 0; k < WPB; ++k) {
             if (wrep[k] != r) {
                 if (r >= 0) push(r, m);
                 r = wrep[k];

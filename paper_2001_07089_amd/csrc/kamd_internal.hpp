@@ -26,6 +26,12 @@ constexpr int CELL_SUBX = 4;             // list cells are sorted in sub-cells o
                                          // cell edge along x (cell_count/start/end per sub-cell)
 constexpr int VH_MAX_BINS = 1024;       // bins of the self van Hove histogram
 constexpr int LIST_UNROLL = 8;           // candidates per step of the list builder's scan
+// Force-kernel windows (mixed precisions): per wavefront and list part at
+// most STAGE_PIECES row pieces (9 stencil rows, each a main run and a wrapped
+// end), staged in LDS as STAGE_SLOTS positions of 12 bytes, of which the last
+// 64 hold the lanes' own positions.
+constexpr int STAGE_PIECES = 18;
+constexpr int STAGE_SLOTS = 1088;
 
 // Neighbour-list layout.  The list of wavefront w is a block of rows * 64
 // ints; entry k of lane l sits at (k / 4) * 256 + l * 4 + k % 4 inside it:
@@ -115,7 +121,11 @@ struct Dev {
     uint32_t *maxdisp;    // per replica: max |r - r_build|^2 (float bits) since the last check
     int32_t *nbr;         // per wave: rows x 64 entries, see list_index
     int2 *kmax;           // per wave: entries of the A part, entries of the B part
-    int2 *lbase;          // per wave and part: base slot of 16-bit entries, or -1 for 32-bit entries
+    int2 *lbase;          // per wave and part: base slot of 16-bit entries, -1 for 32-bit entries,
+                          // or -2 - W: 16-bit offsets into a staged window of W slots
+    int2 *pieces;         // per wave and part: STAGE_PIECES (first slot, slots) of the window's pieces
+    int2 *pcount;         // per wave: pieces of the A part's and the B part's window
+    int32_t stage_ok;     // the force kernels stage windows (mixed precisions)
     int32_t *nlen;        // per slot: true list length (stats)
     // reductions
     double *wred;         // per wave [4]
@@ -168,8 +178,9 @@ hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, boo
 // ignored by the mixed precisions).
 // With energy, also the per-wave partials wred[0..3] = {sum v(t)^2, PE, W,
 // pairs} of the step's end state (v(t) is the closed half kick).
+// wpb: wavefronts per block of the step kernel (1, 2 or 4; an autotuner axis).
 hipError_t launch_force_kd(const Dev &d, const Model &m, int prec, double dt, uint4 *mirror_out, uint32_t *md_out,
-                           double4 *pos4_out, bool energy, hipStream_t s);
+                           double4 *pos4_out, bool energy, int wpb, hipStream_t s);
 // Pack d.x, d.y, d.z into d.pos4 (every slot, padding included).
 hipError_t launch_pack_pos(const Dev &d, hipStream_t s);
 

@@ -477,6 +477,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     int row = 0;  // 32-bit words of the list used so far
     int total = 0;
     int2 kpart = make_int2(0, 0), bpart = make_int2(-1, -1);  // per part: entries, base
+    int2 pcnt = make_int2(0, 0);                              // per part: window pieces (staged)
     int n16 = 0;
     for (int tj = 0; tj < 2; ++tj) {
         const SegInfo &SJ = d.seg[R.seg[tj]];
@@ -491,13 +492,87 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         const double rc16 = sqrt((double)rl2) * (1.0 / 65536.0) + 1.7320508075688772;
         const int r2c = (int)ceil(rc16 * rc16) + 1;
         const double rp2 = rp * rp;
-        // Entries of the part of the particle's own type are stored as 16-bit
-        // offsets from a base slot, two to a 32-bit word, when every slot the
-        // wavefront can accept (the cell rows of its stencils) and its own
-        // slots lie within 2^16 of the lowest of them; otherwise, and for the
-        // other part, as 32-bit slot indices.  base = -1 marks 32-bit entries.
-        int base = -1;
-        if (tj == S.type && SJ.n > 0) {
+        // lowest start and highest end of the lanes' non-empty ranges
+        // (x = INT_MAX when no lane has one); all lanes take part
+        auto span = [&](int st, int en) __attribute__((always_inline)) {
+            const bool has = st < en;
+            return make_int2(-wave_max_all(has ? -st : INT_MIN + 1), wave_max_all(has ? en : -1));
+        };
+        // Slot ranges of one stencil row: the main run of cells, and the end
+        // cell that wraps around the box where the row does.
+        const int32_t *cstart = d.cell_start, *cend = d.cell_end;
+        const int cell0 = SJ.cell0;  // kept in a register across the list stores
+        auto bounds = [&](int oz, int oy) __attribute__((always_inline)) {
+            int4 b = make_int4(0, 0, 0, 0);
+            if (real) {
+                const int qz = (cz + oz + nc) % nc;
+                const int qy = (cy + oy + nc) % nc;
+                const int rowc = cell0 + (qz * nc + qy) * nc;  // cell (0, qy, qz)
+                if (whole) {
+                    b.x = cs(rowc);
+                    b.y = ce(rowc + nc - 1);
+                } else {
+                    // One cell per list radius (reach 1): a particle in
+                    // quarter qx of its cell is more than a cell edge, and
+                    // so more than the list radius, away along x from the
+                    // quarters of the left cell below qx and of the right
+                    // cell above qx; both are left out.
+                    const int a = cx - reach, e = cx + reach;
+                    b.x = cstart[a < 0 ? CELL_SUBX * rowc : CELL_SUBX * (rowc + a) + qx];
+                    b.y = cend[e >= nc ? CELL_SUBX * (rowc + nc) - 1 : CELL_SUBX * (rowc + e) + qx];
+                    // the left cell wraps to the high end of the row, or
+                    // the right cell to its low end
+                    const bool lw = a < 0;
+                    if (lw || e >= nc) {
+                        b.z = cstart[lw ? CELL_SUBX * (rowc + a + nc) + qx : CELL_SUBX * rowc];
+                        b.w = cend[lw ? CELL_SUBX * (rowc + nc) - 1 : CELL_SUBX * (rowc + e - nc) + qx];
+                    }
+                }
+            }
+            return b;
+        };
+        // The force kernels' window (mixed precisions, one cell per list
+        // radius): the wavefront's union span of every row piece, one after
+        // the other, staged in LDS by the force kernel, plus one slot per
+        // lane holding that lane's own position.  Entries of a part whose
+        // window fits are 16-bit window offsets; the padding points at the
+        // lane's own copy (zero separation, skipped like the own slot).  The
+        // pieces are found in a first pass over the rows, since the window
+        // size decides the format of every entry.
+        const int nrow = nz * noff;
+        int wtot = 0, npiece = 0;
+        if (d.stage_ok && SJ.n > 0 && !prune) {
+            int2 *ptab = d.pieces + ((size_t)w * 2 + tj) * STAGE_PIECES;
+            int oz = oz0, oy = -reach;
+            for (int r = 0; r < nrow; ++r) {
+                const int4 b = bounds(oz, oy);
+                const int2 p1 = span(b.x, b.y), p2 = span(b.z, b.w);
+                if (p1.x != INT_MAX) {
+                    if (lane == 0 && npiece < STAGE_PIECES) ptab[npiece] = make_int2(p1.x, p1.y - p1.x);
+                    ++npiece;
+                    wtot += p1.y - p1.x;
+                }
+                if (p2.x != INT_MAX) {
+                    if (lane == 0 && npiece < STAGE_PIECES) ptab[npiece] = make_int2(p2.x, p2.y - p2.x);
+                    ++npiece;
+                    wtot += p2.y - p2.x;
+                }
+                if (++oy == -reach + noff) {
+                    oy = -reach;
+                    ++oz;
+                }
+            }
+        }
+        const bool staged = d.stage_ok && SJ.n > 0 && !prune && npiece <= STAGE_PIECES &&
+                            wtot + WAVE <= STAGE_SLOTS;
+        // Otherwise entries of the part of the particle's own type are stored
+        // as 16-bit offsets from a base slot, two to a 32-bit word, when every
+        // slot the wavefront can accept (the cell rows of its stencils) and
+        // its own slots lie within 2^16 of the lowest of them; else, and for
+        // the other part, as 32-bit slot indices.  base = -1 marks 32-bit
+        // entries; staged windows use base 0.
+        int base = staged ? 0 : -1;
+        if (!staged && tj == S.type && SJ.n > 0) {
             int lo = s, hi = s + 1;
             if (real) {
                 // lowest and highest stencil row (qz * nc + qy) in slot order;
@@ -541,18 +616,21 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         // The particle's own slot passes the test (zero separation) and stays
         // in its list, where the force kernels skip it like the padding.
         // `in` is false only past the end of a range, in the last batch.
+        // The entry of slot j is j + dl: dl = 0 for slot indices, the
+        // piece's offset in the window minus its first slot when staged.
+        int dl = 0;
         auto test = [&](int j, bool in, uint32_t jx, uint32_t jy, uint32_t jz) __attribute__((always_inline)) {
             const float dx = (float)(int)(mi.x - jx);
             const float dy = (float)(int)(mi.y - jy);
             const float dz = (float)(int)(mi.z - jz);
             const float r2 = dx * dx + dy * dy + dz * dz;
             const int acc = (int)in & (int)(r2 < rl2);
-            buf[cnt & (LIST_STAGE - 1)][lane] = j;
+            buf[cnt & (LIST_STAGE - 1)][lane] = j + dl;
             cnt += acc;
         };
         auto test_coarse = [&](int j, bool in, uint32_t jxy, uint32_t jz) __attribute__((always_inline)) {
             const int acc = (int)in & (int)(r2_coarse(ixy, iz, jxy, jz) < r2c);
-            buf[cnt & (LIST_STAGE - 1)][lane] = j;
+            buf[cnt & (LIST_STAGE - 1)][lane] = j + dl;
             cnt += acc;
         };
         auto scan = [&](int st, int en) __attribute__((always_inline)) {  // straight from global memory
@@ -575,12 +653,6 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                 for (int u = 0; u < LIST_UNROLL; ++u) test(j + u, j + u < en, mj[u].x, mj[u].y, mj[u].z);
             }
             if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
-        };
-        // lowest start and highest end of the lanes' non-empty ranges
-        // (x = INT_MAX when no lane has one); all lanes take part
-        auto span = [&](int st, int en) __attribute__((always_inline)) {
-            const bool has = st < en;
-            return make_int2(-wave_max_all(has ? -st : INT_MIN + 1), wave_max_all(has ? en : -1));
         };
         auto scan_staged = [&](int st, int en, int2 sp) __attribute__((always_inline)) {
             const int lo = sp.x, hi = sp.y;
@@ -688,40 +760,11 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             // end cell that wraps around the box where the row does.  Rows
             // are read one step ahead of their scan, so that the loads of a
             // row's bounds overlap the staging loads of the row before.
-            const int32_t *cstart = d.cell_start, *cend = d.cell_end;
-            const int cell0 = SJ.cell0;  // kept in a register across the list stores
-            auto bounds = [&](int oz, int oy) __attribute__((always_inline)) {
-                int4 b = make_int4(0, 0, 0, 0);
-                if (real) {
-                    const int qz = (cz + oz + nc) % nc;
-                    const int qy = (cy + oy + nc) % nc;
-                    const int rowc = cell0 + (qz * nc + qy) * nc;  // cell (0, qy, qz)
-                    if (whole) {
-                        b.x = cs(rowc);
-                        b.y = ce(rowc + nc - 1);
-                    } else {
-                        // One cell per list radius (reach 1): a particle in
-                        // quarter qx of its cell is more than a cell edge, and
-                        // so more than the list radius, away along x from the
-                        // quarters of the left cell below qx and of the right
-                        // cell above qx; both are left out.
-                        const int a = cx - reach, e = cx + reach;
-                        b.x = cstart[a < 0 ? CELL_SUBX * rowc : CELL_SUBX * (rowc + a) + qx];
-                        b.y = cend[e >= nc ? CELL_SUBX * (rowc + nc) - 1 : CELL_SUBX * (rowc + e) + qx];
-                        // the left cell wraps to the high end of the row, or
-                        // the right cell to its low end
-                        const bool lw = a < 0;
-                        if (lw || e >= nc) {
-                            b.z = cstart[lw ? CELL_SUBX * (rowc + a + nc) + qx : CELL_SUBX * rowc];
-                            b.w = cend[lw ? CELL_SUBX * (rowc + nc) - 1 : CELL_SUBX * (rowc + e - nc) + qx];
-                        }
-                    }
-                }
-                return b;
-            };
-            const int nrow = nz * noff;
+            // Rows are read one step ahead of their scan, so that the loads
+            // of a row's bounds overlap the staging loads of the row before.
             int oz = oz0, oy = -reach;
             int4 next = bounds(oz, oy);
+            int woff = 0;  // window offset of the next piece (staged)
             for (int r = 0; r < nrow; ++r) {
                 const int4 cur = next;
                 const int2 sp1 = span(cur.x, cur.y), sp2 = span(cur.z, cur.w);
@@ -735,12 +778,23 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                     if (++oz == oz0 + nz) oz = oz0;
                 }
                 next = bounds(oz, oy);
+                if (staged && sp1.x != INT_MAX) {
+                    dl = woff - sp1.x;
+                    woff += sp1.y - sp1.x;
+                }
                 scan_staged(cur.x, cur.y, sp1);
+                if (staged && sp2.x != INT_MAX) {
+                    dl = woff - sp2.x;
+                    woff += sp2.y - sp2.x;
+                }
                 scan_staged(cur.z, cur.w, sp2);
             }
+            dl = 0;
         }
         flush();
         total += cnt;
+        // padding: the own slot, or in a window the lane's own position copy
+        const int padv = staged ? wtot + lane : s;
         int kmax = wave_max_all(cnt);
         const int align = half ? 2 * LIST_ROW_ALIGN : LIST_ROW_ALIGN;  // whole 16-byte words
         kmax = (kmax + align - 1) / align * align;
@@ -748,14 +802,14 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             const int k = row + (half ? done / 2 : done);
             int e[8];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) e[t] = done + t < cnt ? buf[(done + t) & (LIST_STAGE - 1)][lane] : s;
+            for (int t = 0; t < 8; ++t) e[t] = done + t < cnt ? buf[(done + t) & (LIST_STAGE - 1)][lane] : padv;
             const int4 q = half ? make_int4(pack(e[0], e[1]), pack(e[2], e[3]), pack(e[4], e[5]), pack(e[6], e[7]))
                                 : make_int4(e[0], e[1], e[2], e[3]);
             if (k < rows) *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = q;
             done += group;
         }
         const int words = half ? kmax / 2 : kmax;  // 32-bit words the part occupies
-        const int pad = half ? pack(s, s) : s;
+        const int pad = half ? pack(padv, padv) : padv;
         for (int k = row + (half ? done / 2 : done); k < row + words && k < rows; k += 4)
             *reinterpret_cast<int4 *>(col + (k >> 2) * 256) = make_int4(pad, pad, pad, pad);
         if (row + words > rows && lane == 0) set_err(d.err, KAMD_DEV_LIST_OVERFLOW);
@@ -763,21 +817,26 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         // live in scratch memory when this loop is not unrolled
         kpart.x = tj == 0 ? kmax : kpart.x;
         kpart.y = tj == 1 ? kmax : kpart.y;
-        bpart.x = tj == 0 ? base : bpart.x;
-        bpart.y = tj == 1 ? base : bpart.y;
-        if (half) n16 = cnt - 1;  // 16-bit partner entries (the own slot is one of the cnt)
+        const int code = staged ? -2 - wtot : base;  // <= -2: a staged window of -2 - code slots
+        bpart.x = tj == 0 ? code : bpart.x;
+        bpart.y = tj == 1 ? code : bpart.y;
+        pcnt.x = tj == 0 ? (staged ? npiece : 0) : pcnt.x;
+        pcnt.y = tj == 1 ? (staged ? npiece : 0) : pcnt.y;
+        if (half) n16 += cnt - (tj == S.type ? 1 : 0);  // 16-bit partner entries (not the own slot)
         row += words;
     }
     if (row > rows) {  // keep the force kernels inside the list
         if (lane == 0) atomicMax(&d.counters[3], row);  // the rows a healing rebuild must provide
-        const int w0 = min(bpart.x >= 0 ? kpart.x / 2 : kpart.x, rows);
-        const int w1 = min(bpart.y >= 0 ? kpart.y / 2 : kpart.y, rows - w0);
-        kpart.x = bpart.x >= 0 ? 2 * w0 : w0;
-        kpart.y = bpart.y >= 0 ? 2 * w1 : w1;
+        const bool h0 = bpart.x >= 0 || bpart.x <= -2, h1 = bpart.y >= 0 || bpart.y <= -2;  // 16-bit parts
+        const int w0 = min(h0 ? kpart.x / 2 : kpart.x, rows);
+        const int w1 = min(h1 ? kpart.y / 2 : kpart.y, rows - w0);
+        kpart.x = h0 ? 2 * w0 : w0;
+        kpart.y = h1 ? 2 * w1 : w1;
     }
     if (lane == 0) {
         d.kmax[w] = kpart;
         d.lbase[w] = bpart;
+        d.pcount[w] = pcnt;
     }
     // partners (without the own slot) in the low 16 bits, those of them
     // stored as 16-bit entries in the high 16 bits

@@ -95,12 +95,12 @@ __global__ __launch_bounds__(BLOCK) void k_pack_pos(Dev d)
 // pos4_out (a different buffer), where the next step's neighbours find them.
 // Padding slots copy their unchanged position, which keeps their own list
 // entry at zero separation.
-template <bool ENERGY, bool KD>
-__global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_inc, double dt, uint4 *mirror_out,
-                                                       uint32_t *md_out, double4 *pos4_out)
+template <bool ENERGY, bool KD, int WPB>
+__global__ __launch_bounds__(WAVE * WPB) void k_force_fp64(Dev d, Model m, int step_inc, double dt,
+                                                            uint4 *mirror_out, uint32_t *md_out, double4 *pos4_out)
 {
     close_step(d, step_inc);
-    const int w = wave_id_remapped();
+    const int w = wave_id_remapped<WPB>();
     const bool valid = w < d.nwaves;
     float d2 = 0.0f;
     int rep = -1;
@@ -154,7 +154,9 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
 #pragma unroll
             for (int u = 0; u < 4; ++u) pair(pj[u].x, pj[u].y, pj[u].z);
         };
-        if (base >= 0) {
+        if (base <= -2) {  // a window list is never built for FP64
+            if (lane_id() == 0) set_err(d.err, KAMD_DEV_LIST_FORMAT);
+        } else if (base >= 0) {
             for (int k = 0; k < nrows; k += 4) {
                 int jj[4];
                 list_quad16(nb, k, base, jj);
@@ -206,7 +208,14 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
         }
     }
     }
-    if (KD) block_disp_max(md_out, valid, rep, d2);
+    if (KD) block_disp_max<WPB>(md_out, valid, rep, d2);
+}
+
+// LDS visible to the whole wavefront (the lanes wrote it, others read it).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
 }
 
 // KD (NVE steps only): after the force of slot s, close the step with the
@@ -214,12 +223,22 @@ __global__ __launch_bounds__(BLOCK) void k_force_fp64(Dev d, Model m, int step_i
 // new mirror into mirror_out, displacement into md_out) in the same pass.
 // Neighbours read their positions from d.mirror while mirror_out receives the
 // new ones, so the two must be different buffers; the forces are not stored.
-template <bool FIXED, bool ENERGY, bool KD>
-__global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_inc, double dt,
-                                                        uint4 *mirror_out, uint32_t *md_out)
+//
+// STAGE: a list part whose wavefront window fits (lbase <= -2, written by the
+// list builder) is gathered from LDS.  The wavefront first copies the slot
+// ranges of the part's row pieces (its lanes' union span of each stencil
+// row, coalesced loads of d.mirror) one after the other into its window, and
+// each lane its own position after them; the entries are 16-bit offsets into
+// that window.  A gather from global memory costs the kernel one cache-line
+// access per lane and waits on the vector L1; a window read does neither.
+// Parts whose window does not fit keep the slot-index entries.
+template <bool FIXED, bool ENERGY, bool KD, bool STAGE, int WPB>
+__global__ __launch_bounds__(WAVE * WPB) void k_force_mixed(Dev d, Model m, int step_inc, double dt,
+                                                             uint4 *mirror_out, uint32_t *md_out)
 {
+    __shared__ uint32_t swin[STAGE ? WPB : 1][STAGE ? 3 * STAGE_SLOTS : 1];
     close_step(d, step_inc);
-    const int w = wave_id_remapped();
+    const int w = wave_id_remapped<WPB>();
     const bool valid = w < d.nwaves;
     float d2 = 0.0f;
     int rep = -1;
@@ -231,6 +250,8 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
     const uint4 mi = d.mirror[s];
     const int2 km = d.kmax[w];
     const int2 lb = d.lbase[w];
+    const int2 pc = STAGE ? d.pcount[w] : make_int2(0, 0);
+    uint32_t *win = swin[STAGE ? threadIdx.x >> 6 : 0];
     double fx = 0.0, fy = 0.0, fz = 0.0, pe = 0.0, vir = 0.0, npair = 0.0, ke2 = 0.0;
     uint64_t qx = 0, qy = 0, qz = 0;
     bool range_bad = false;
@@ -282,7 +303,43 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
 #pragma unroll
             for (int u = 0; u < 4; ++u) pair(mj[u]);
         };
-        if (base >= 0) {
+        if (!STAGE && base <= -2) {  // a window list for the direct variant: never read it as slots
+            if (lane_id() == 0) set_err(d.err, KAMD_DEV_LIST_FORMAT);
+        } else if (STAGE && base <= -2) {
+            const int W = -2 - base;
+            const int np = tj ? pc.y : pc.x;
+            const int2 *pt = d.pieces + ((size_t)w * 2 + tj) * STAGE_PIECES;
+            int off = 0;
+            for (int q = 0; q < np; ++q) {
+                const int2 pq = pt[q];
+                for (int e = lane_id(); e < pq.y; e += WAVE) {
+                    const uint4 mj = d.mirror[pq.x + e];
+                    uint32_t *o = win + 3 * (off + e);
+                    o[0] = mj.x;
+                    o[1] = mj.y;
+                    o[2] = mj.z;
+                }
+                off += pq.y;
+            }
+            uint32_t *o = win + 3 * (W + lane_id());
+            o[0] = mi.x;
+            o[1] = mi.y;
+            o[2] = mi.z;
+            wave_lds_sync();
+            for (int k = 0; k < nrows; k += 4) {
+                int jj[4];
+                list_quad16(nb, k, 0, jj);
+                uint4 mj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t *src = win + 3 * jj[u];
+                    mj[u] = make_uint4(src[0], src[1], src[2], 0u);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) pair(mj[u]);
+            }
+            wave_lds_sync();  // the next part stages over this window
+        } else if (base >= 0) {
             for (int k = 0; k < nrows; k += 4) {
                 int jj[4];
                 list_quad16(nb, k, base, jj);
@@ -312,7 +369,7 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
             vir += 0.5 * 48.0 * m.eps[p] * (double)sv;
             npair += (double)cnt;
         }
-        row += base >= 0 ? nrows / 2 : nrows;
+        row += base != -1 ? nrows / 2 : nrows;  // 16-bit entries: base >= 0, or a staged window
     }
     if (FIXED) {
         const double inv = 1.0 / FIX_SCALE;
@@ -349,35 +406,64 @@ __global__ __launch_bounds__(BLOCK) void k_force_mixed(Dev d, Model m, int step_
         }
     }
     }
-    if (KD) block_disp_max(md_out, valid, rep, d2);
+    if (KD) block_disp_max<WPB>(md_out, valid, rep, d2);
 }
 
+// The mixed kernel with or without windows (as the lists were built), in
+// blocks of WPB wavefronts.
+template <bool FIXED, bool ENERGY, bool KD, int WPB>
+static void launch_mixed_wpb(const Dev &d, const Model &m, int si, double dt, uint4 *mirror_out, uint32_t *md_out,
+                             hipStream_t s)
+{
+    const int nb = (d.nwaves + WPB - 1) / WPB;
+    if (d.stage_ok)
+        hipLaunchKernelGGL((k_force_mixed<FIXED, ENERGY, KD, true, WPB>), dim3(nb), dim3(WAVE * WPB), 0, s, d, m, si,
+                           dt, mirror_out, md_out);
+    else
+        hipLaunchKernelGGL((k_force_mixed<FIXED, ENERGY, KD, false, WPB>), dim3(nb), dim3(WAVE * WPB), 0, s, d, m,
+                           si, dt, mirror_out, md_out);
+}
+
+template <bool FIXED, bool ENERGY, bool KD>
+static void launch_mixed(const Dev &d, const Model &m, int si, double dt, uint4 *mirror_out, uint32_t *md_out,
+                         int wpb, hipStream_t s)
+{
+    if (wpb == 1) launch_mixed_wpb<FIXED, ENERGY, KD, 1>(d, m, si, dt, mirror_out, md_out, s);
+    else if (wpb == 2) launch_mixed_wpb<FIXED, ENERGY, KD, 2>(d, m, si, dt, mirror_out, md_out, s);
+    else launch_mixed_wpb<FIXED, ENERGY, KD, 4>(d, m, si, dt, mirror_out, md_out, s);
+}
+
+template <bool ENERGY, bool KD, int WPB>
+static void launch_fp64_wpb(const Dev &d, const Model &m, int si, double dt, uint4 *mirror_out, uint32_t *md_out,
+                            double4 *pos4_out, hipStream_t s)
+{
+    const int nb = (d.nwaves + WPB - 1) / WPB;
+    hipLaunchKernelGGL((k_force_fp64<ENERGY, KD, WPB>), dim3(nb), dim3(WAVE * WPB), 0, s, d, m, si, dt, mirror_out,
+                       md_out, pos4_out);
+}
+
+// Force-only launches (md_forces, the last step of a call, Nose-Hoover):
+// blocks of WAVES_PER_BLOCK wavefronts.
 hipError_t launch_force(const Dev &d, const Model &m, int prec, bool energy, bool step_inc, hipStream_t s)
 {
-    const int nb = (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
     const int si = step_inc ? 1 : 0;
+    constexpr int W4 = WAVES_PER_BLOCK;
     if (prec == 0) {
         hipLaunchKernelGGL(k_pack_pos, dim3((d.npad_total + BLOCK - 1) / BLOCK), dim3(BLOCK), 0, s, d);
         if (energy)
-            hipLaunchKernelGGL((k_force_fp64<true, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
-                               (uint4 *)nullptr, (uint32_t *)nullptr, (double4 *)nullptr);
+            launch_fp64_wpb<true, false, W4>(d, m, si, 0.0, nullptr, nullptr, nullptr, s);
         else
-            hipLaunchKernelGGL((k_force_fp64<false, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
-                               (uint4 *)nullptr, (uint32_t *)nullptr, (double4 *)nullptr);
+            launch_fp64_wpb<false, false, W4>(d, m, si, 0.0, nullptr, nullptr, nullptr, s);
     } else if (prec == 1) {
         if (energy)
-            hipLaunchKernelGGL((k_force_mixed<false, true, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
-                               (uint4 *)nullptr, (uint32_t *)nullptr);
+            launch_mixed_wpb<false, true, false, W4>(d, m, si, 0.0, nullptr, nullptr, s);
         else
-            hipLaunchKernelGGL((k_force_mixed<false, false, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
-                               (uint4 *)nullptr, (uint32_t *)nullptr);
+            launch_mixed_wpb<false, false, false, W4>(d, m, si, 0.0, nullptr, nullptr, s);
     } else {
         if (energy)
-            hipLaunchKernelGGL((k_force_mixed<true, true, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
-                               (uint4 *)nullptr, (uint32_t *)nullptr);
+            launch_mixed_wpb<true, true, false, W4>(d, m, si, 0.0, nullptr, nullptr, s);
         else
-            hipLaunchKernelGGL((k_force_mixed<true, false, false>), dim3(nb), dim3(BLOCK), 0, s, d, m, si, 0.0,
-                               (uint4 *)nullptr, (uint32_t *)nullptr);
+            launch_mixed_wpb<true, false, false, W4>(d, m, si, 0.0, nullptr, nullptr, s);
     }
     return hipGetLastError();
 }
@@ -389,31 +475,30 @@ hipError_t launch_pack_pos(const Dev &d, hipStream_t s)
 }
 
 hipError_t launch_force_kd(const Dev &d, const Model &m, int prec, double dt, uint4 *mirror_out, uint32_t *md_out,
-                           double4 *pos4_out, bool energy, hipStream_t s)
+                           double4 *pos4_out, bool energy, int wpb, hipStream_t s)
 {
-    const int nb = (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
     if (prec == 0) {
         if (!d.pos4 || !pos4_out || pos4_out == d.pos4) return hipErrorInvalidValue;
-        if (energy)
-            hipLaunchKernelGGL((k_force_fp64<true, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out,
-                               md_out, pos4_out);
-        else
-            hipLaunchKernelGGL((k_force_fp64<false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt, mirror_out,
-                               md_out, pos4_out);
+        if (energy) {
+            if (wpb == 1) launch_fp64_wpb<true, true, 1>(d, m, 1, dt, mirror_out, md_out, pos4_out, s);
+            else if (wpb == 2) launch_fp64_wpb<true, true, 2>(d, m, 1, dt, mirror_out, md_out, pos4_out, s);
+            else launch_fp64_wpb<true, true, 4>(d, m, 1, dt, mirror_out, md_out, pos4_out, s);
+        } else {
+            if (wpb == 1) launch_fp64_wpb<false, true, 1>(d, m, 1, dt, mirror_out, md_out, pos4_out, s);
+            else if (wpb == 2) launch_fp64_wpb<false, true, 2>(d, m, 1, dt, mirror_out, md_out, pos4_out, s);
+            else launch_fp64_wpb<false, true, 4>(d, m, 1, dt, mirror_out, md_out, pos4_out, s);
+        }
     } else if (prec == 1) {
         if (energy)
-            hipLaunchKernelGGL((k_force_mixed<false, true, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt,
-                               mirror_out, md_out);
+            launch_mixed<false, true, true>(d, m, 1, dt, mirror_out, md_out, wpb, s);
         else
-            hipLaunchKernelGGL((k_force_mixed<false, false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt,
-                               mirror_out, md_out);
+            launch_mixed<false, false, true>(d, m, 1, dt, mirror_out, md_out, wpb, s);
     } else if (prec == 2) {
         if (energy)
-            hipLaunchKernelGGL((k_force_mixed<true, true, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt,
-                               mirror_out, md_out);
+            launch_mixed<true, true, true>(d, m, 1, dt, mirror_out, md_out, wpb, s);
         else
-            hipLaunchKernelGGL((k_force_mixed<true, false, true>), dim3(nb), dim3(BLOCK), 0, s, d, m, 1, dt,
-                               mirror_out, md_out);
+            launch_mixed<true, false, true>(d, m, 1, dt, mirror_out, md_out, wpb, s);
     } else {
         return hipErrorInvalidValue;
     }

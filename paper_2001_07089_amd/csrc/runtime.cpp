@@ -83,6 +83,8 @@ struct kamd_ctx {
     int64_t graph_steps = 0;
     Plan plan;                        // the current list parameters' layout
     Shape shape;                      // sizes of the workspace's fixed part
+    bool stage_windows = false;       // mixed-precision force kernels gather from LDS windows
+    int force_wpb = WAVES_PER_BLOCK;  // wavefronts per block of the step kernel
     std::string err = "no error";
 };
 
@@ -387,6 +389,8 @@ static void carve_fixed(Dev &d, CtxBufs &b, const Shape &z, Carve &k)
     b.md_base = k.take<uint32_t>(2 * z.nrep);
     d.kmax = k.take<int2>(z.nwaves);
     d.lbase = k.take<int2>(z.nwaves);
+    d.pieces = k.take<int2>(z.nwaves * 2 * STAGE_PIECES);
+    d.pcount = k.take<int2>(z.nwaves);
     d.wred = k.take<double>(4 * z.nwaves);
     d.rsum = k.take<double>(4 * z.nrep);
     d.obs = k.take<double>(8 * z.nrep);
@@ -526,6 +530,7 @@ static void bind_workspace(kamd_ctx *c, const Plan &P)
     d.rows = P.rows;
     d.ncells = P.ncells;
     d.rdf_cells_cap = (int64_t)c->shape.rdf_cells;
+    d.stage_ok = c->cfg.precision != KAMD_PREC_FP64 && c->stage_windows;
     d.ring_cap = ring_rows(&c->cfg);
     d.msd_slots = (int32_t)c->shape.msd_slots;
 }
@@ -551,6 +556,7 @@ static int init_fixed(kamd_ctx *c)
     HIPCHK(c, launch_zero_i32((int32_t *)c->md_base, 2 * nr, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)d.kmax, 2 * nw, c->stream));
     HIPCHK(c, launch_fill_i32((int32_t *)d.lbase, 2 * nw, -1, c->stream));
+    HIPCHK(c, launch_zero_i32((int32_t *)d.pcount, 2 * nw, c->stream));
     HIPCHK(c, launch_zero_f64(d.wred, 4 * nw, c->stream));
     HIPCHK(c, launch_zero_f64((double *)d.dyn, (int64_t)(sizeof(RepDyn) / 8) * nr, c->stream));
     HIPCHK(c, launch_zero_i32((int32_t *)d.err, 4, c->stream));
@@ -809,7 +815,7 @@ static int enqueue_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb
             // list build reorders them with the rest); otherwise pack them
             if (prec == KAMD_PREC_FP64 && !p4_ok) HIPCHK(c, launch_pack_pos(dd, c->stream));
             HIPCHK(c, launch_force_kd(dd, c->model, prec, dt, mir[1 - cur], c->md_base + (1 - par) * c->d.nrep,
-                                      p4[1 - cur], smp, c->stream));
+                                      p4[1 - cur], smp, c->force_wpb, c->stream));
             if (smp) {
                 HIPCHK(c, launch_rep_reduce(dd, 7, c->stream));
                 HIPCHK(c, launch_sample(dd, 7, c->stream));
@@ -1379,6 +1385,27 @@ extern "C" int md_set_list_params(kamd_ctx *c, double skin, int32_t cell_div)
     return apply_list_params(c, skin, cell_div, false);
 }
 
+extern "C" int md_set_force_kernel(kamd_ctx *c, int32_t windows, int32_t wg_size)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    if (windows != 0 && windows != 1) return fail(c, KAMD_EINVAL, "windows must be 0 or 1");
+    if (windows && c->cfg.precision == KAMD_PREC_FP64)
+        return fail(c, KAMD_EINVAL, "the FP64 force kernel has no window variant");
+    if (wg_size != 0 && wg_size != 64 && wg_size != 128 && wg_size != 256)
+        return fail(c, KAMD_EINVAL, "wg_size must be 0, 64, 128 or 256");
+    const int wpb = wg_size ? wg_size / WAVE : c->force_wpb;
+    if (c->stage_windows == (windows != 0) && c->force_wpb == wpb) return KAMD_OK;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    drop_graph(c);                  // its launches carry the old kernel and Dev
+    c->force_wpb = wpb;
+    if (c->stage_windows != (windows != 0)) {
+        c->stage_windows = windows != 0;
+        c->d.stage_ok = c->cfg.precision != KAMD_PREC_FP64 && c->stage_windows;
+        return force_rebuild_all(c);  // the entries change format at the next build
+    }
+    return KAMD_OK;
+}
+
 extern "C" int md_workspace_needed(kamd_ctx *c, size_t *bytes)
 {
     if (!c || !bytes) return fail(c, KAMD_EINVAL, "null argument");
@@ -1420,9 +1447,13 @@ extern "C" int md_stats(kamd_ctx *c, double *host_out)
     int32_t cnt[8];
     HIPCHK(c, hipMemcpyAsync(cnt, c->d.counters, 32, hipMemcpyDeviceToHost, c->stream));
     std::vector<int32_t> nlen(c->d.npad_total), id(c->d.npad_total);
+    std::vector<int2> lb(c->d.nwaves);
     HIPCHK(c, hipMemcpyAsync(nlen.data(), c->d.nlen, 4 * nlen.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(id.data(), c->d.id, 4 * id.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(lb.data(), c->d.lbase, sizeof(int2) * lb.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    int64_t parts_staged = 0;
+    for (const int2 &b : lb) parts_staged += (b.x <= -2) + (b.y <= -2);
     double sum = 0.0, mx = 0.0, bytes = 0.0;
     int64_t cntr = 0;
     for (size_t i = 0; i < nlen.size(); ++i)
@@ -1442,6 +1473,9 @@ extern "C" int md_stats(kamd_ctx *c, double *host_out)
     host_out[6] = c->skin;
     host_out[7] = (double)c->cell_div;
     host_out[8] = cntr ? bytes / cntr : 0.0;
+    host_out[9] = c->d.stage_ok ? 1.0 : 0.0;
+    host_out[10] = lb.empty() ? 0.0 : (double)parts_staged / (2.0 * lb.size());
+    host_out[11] = (double)(WAVE * c->force_wpb);
     return KAMD_OK;
 }
 
@@ -1666,7 +1700,7 @@ extern "C" int md_profile(kamd_ctx *c, int32_t nsteps, double *host_out)
         if (fused[s]) {
             if (prec == KAMD_PREC_FP64 && !p4_ok) HIPCHK(c, launch_pack_pos(dd, c->stream));
             HIPCHK(c, launch_force_kd(dd, c->model, prec, dt, mir[1 - cur], c->md_base + (1 - par) * c->d.nrep,
-                                      p4[1 - cur], false, c->stream));
+                                      p4[1 - cur], false, c->force_wpb, c->stream));
             cur = 1 - cur;
             par = 1 - par;
             need_drift = false;

@@ -22,7 +22,7 @@ PREC_FP64, PREC_MIXED, PREC_MIXED_FIXED = 0, 1, 2
 F_FORCE, F_ENERGY, F_VIRIAL = 1, 2, 4
 NVT_STOCHASTIC, NVT_NOSE_HOOVER = 0, 1
 INIT_GIVEN, INIT_RSA, INIT_LATTICE = 0, 1, 2
-DEV_NONFINITE, DEV_LIST_OVERFLOW, DEV_FORCE_RANGE = 1, 2, 4
+DEV_NONFINITE, DEV_LIST_OVERFLOW, DEV_FORCE_RANGE, DEV_LIST_FORMAT = 1, 2, 4, 8
 PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED, "mixed_fixed": PREC_MIXED_FIXED}
 
 # Kob-Andersen parameters (Sec. II.B), pair order AA, AB, BB.
@@ -35,7 +35,8 @@ EXPORTED = ("md_workspace_size", "md_admit", "md_init", "md_build_cells", "md_fo
             "md_import", "md_graph_capture", "md_graph_launch", "md_autotune", "md_set_list_params",
             "md_stats", "md_get_state", "md_set_state", "md_profile", "md_status", "md_last_error", "md_destroy",
             "md_log_schedule", "md_set_temperature", "md_scale_velocities", "md_van_hove",
-            "md_observables_now", "md_clear_samples", "md_workspace_needed", "md_set_workspace")
+            "md_observables_now", "md_clear_samples", "md_workspace_needed", "md_set_workspace",
+            "md_set_force_kernel")
 
 
 class KamdError(RuntimeError):
@@ -99,6 +100,7 @@ def lib():
             "md_graph_launch": [P],
             "md_autotune": [P, i32, P],
             "md_set_list_params": [P, f64, i32],
+            "md_set_force_kernel": [P, i32, i32],
             "md_stats": [P, P],
             "md_get_state": [P, P, C.POINTER(C.c_size_t)],
             "md_set_state": [P, P, C.c_size_t],
@@ -308,11 +310,15 @@ def md_set_list_params(ctx, skin: float, cell_div: int):
     _check(lib().md_set_list_params(ctx, float(skin), int(cell_div)), ctx)
 
 
+def md_set_force_kernel(ctx, windows: int, wg_size: int = 0):
+    _check(lib().md_set_force_kernel(ctx, int(windows), int(wg_size)), ctx)
+
+
 def md_stats(ctx):
-    out = np.zeros(9)
+    out = np.zeros(12)
     _check(lib().md_stats(ctx, out.ctypes.data), ctx)
     keys = ("steps", "rebuilds", "n_total", "list_rows", "mean_list_len", "max_list_len", "skin", "cell_div",
-            "mean_list_bytes")
+            "mean_list_bytes", "windows", "staged_fraction", "wg_size")
     return dict(zip(keys, out.tolist()))
 
 

@@ -737,12 +737,21 @@ def test_list_statistics_count_16bit_entries():
     0.2 * 2 + 0.8 * 4 for B, 2.6 on average."""
     log("case list statistics")
     s = system([(2000, 1.0, 3, 1.2)], "mixed_fixed")
+    md.md_set_force_kernel(s.ctx, 0)          # slot-index entries
     s.forces()
     st = md.md_stats(s.ctx)
     ratio = st["mean_list_bytes"] / st["mean_list_len"]
     log(f"  bytes per partner {ratio:.3f}")
     assert 2.3 < ratio < 3.0
     assert st["max_list_len"] <= st["list_rows"]
+    assert st["windows"] == 0 and st["staged_fraction"] == 0
+    # window entries are 16-bit offsets: 2 bytes per partner where a part's
+    # window fits (every part of so small a box)
+    md.md_set_force_kernel(s.ctx, 1)
+    s.forces()
+    st = md.md_stats(s.ctx)
+    assert st["windows"] == 1 and st["staged_fraction"] == 1.0
+    assert st["mean_list_bytes"] / st["mean_list_len"] == pytest.approx(2.0)
     s.close()
 
 
