@@ -187,6 +187,20 @@ typedef struct kamd_ctx kamd_ctx;
 int md_init(kamd_ctx **out, const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
             const kamd_state *st, void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): md_init with the
+ * workspace taken from a fixed 64 MiB device array that the library holds
+ * per GPU until the process ends (about 43,000 particles with the default
+ * 16 MSD origin slots, more with fewer).  Allocates no
+ * device memory and calls no allocating routine.  KAMD_ENOMEM when
+ * md_workspace_size exceeds 64 MiB; KAMD_ESTATE while another context works
+ * in the current device's array (one at a time: two would overwrite each
+ * other; md_destroy releases it).  A list that outgrows the array later is
+ * reported as by a caller-owned workspace (KAMD_ENOMEM).  Everything else is
+ * md_init's. */
+int md_init_static(kamd_ctx **out, const kamd_config *cfg, const kamd_replica *reps, int32_t n_rep,
+                   const kamd_state *st, void *hip_stream);
+
 /* Workspace the context needs now (host memory *bytes): more than it has
  * after a refused md_set_list_params or md_autotune, or after a neighbour
  * list outgrew its rows in a caller-owned workspace (those calls return

@@ -26,6 +26,7 @@ SOURCES = {
     "kernels_force.hip": [],
     "kernels_step.hip": [],
     "kernels_analysis.hip": ["-ffp-contract=off"],
+    "static_ws.hip": [],
     "runtime.cpp": [],
 }
 

@@ -160,6 +160,12 @@ struct Dev {
 };
 
 
+// The static workspace (static_ws.hip): the runtime tells it when a context
+// that used a device's array is destroyed.
+void release_static_workspace(int device);
+void set_init_error(const char *msg);
+void mark_static(kamd_ctx *c, int device);
+
 // ---------------------------------------------------------------- launchers
 // Each returns hipGetLastError() after its launch(es).
 hipError_t launch_rb_gate(const Dev &d, hipStream_t s);

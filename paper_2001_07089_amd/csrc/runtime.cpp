@@ -83,6 +83,7 @@ struct kamd_ctx {
     int64_t graph_steps = 0;
     Plan plan;                        // the current list parameters' layout
     Shape shape;                      // sizes of the workspace's fixed part
+    int static_device = -1;           // >= 0: the workspace is that device's static array
     bool stage_windows = false;       // mixed-precision force kernels gather from LDS windows
     int force_wpb = WAVES_PER_BLOCK;  // wavefronts per block of the step kernel
     std::string err = "no error";
@@ -972,6 +973,13 @@ static int heal_steps(kamd_ctx *c, int nsteps, int ensemble, int mode, int nb)
 // ------------------------------------------------------------------ C ABI
 extern "C" const char *md_last_error(const kamd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_init_error.c_str(); }
 
+namespace kamd {
+// For md_init_static: the message md_last_error(NULL) returns after a refusal,
+// and the mark that makes md_destroy hand the static array back.
+void set_init_error(const char *msg) { g_init_error = msg; }
+void mark_static(kamd_ctx *c, int device) { c->static_device = device; }
+}  // namespace kamd
+
 // Adopt a skin and cell division (and the list rows of a healed overflow):
 // the plan, the tables, and (after md_init) the cell and list part of the
 // workspace, which grows when it must.  Forces a full rebuild at the next
@@ -1774,6 +1782,7 @@ extern "C" int md_destroy(kamd_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     drop_graph(c);
     if (c->ws_owned && c->ws) (void)hipFree(c->ws);
+    if (c->static_device >= 0) release_static_workspace(c->static_device);
     c->ws = nullptr;
     delete c;
     return KAMD_OK;

@@ -36,7 +36,7 @@ EXPORTED = ("md_workspace_size", "md_admit", "md_init", "md_build_cells", "md_fo
             "md_stats", "md_get_state", "md_set_state", "md_profile", "md_status", "md_last_error", "md_destroy",
             "md_log_schedule", "md_set_temperature", "md_scale_velocities", "md_van_hove",
             "md_observables_now", "md_clear_samples", "md_workspace_needed", "md_set_workspace",
-            "md_set_force_kernel")
+            "md_init_static", "md_set_force_kernel")
 
 
 class KamdError(RuntimeError):
@@ -83,6 +83,7 @@ def lib():
             "md_admit": [C.POINTER(Config), P, i32, C.c_size_t, P, C.POINTER(i32)],
             "md_init": [C.POINTER(P), C.POINTER(Config), P, i32, C.POINTER(State), P, C.c_size_t, P],
             "md_workspace_needed": [P, C.POINTER(C.c_size_t)],
+            "md_init_static": [C.POINTER(P), C.POINTER(Config), P, i32, C.POINTER(State), P],
             "md_set_workspace": [P, P, C.c_size_t],
             "md_build_cells": [P],
             "md_forces": [P, u32, P],
@@ -200,6 +201,14 @@ def md_init(cfg: Config, reps, state: State, stream: int, workspace: int = 0, ws
     ctx = C.c_void_p()
     _check(lib().md_init(C.byref(ctx), C.byref(cfg), C.cast(reps, C.c_void_p), len(reps), C.byref(state),
                          C.c_void_p(workspace or None), int(ws_bytes), C.c_void_p(stream)))
+    return ctx
+
+
+def md_init_static(cfg: Config, reps, state: State, stream: int):
+    """md_init in the library's fixed per-device array (no device allocation)."""
+    ctx = C.c_void_p()
+    _check(lib().md_init_static(C.byref(ctx), C.byref(cfg), C.cast(reps, C.c_void_p), len(reps), C.byref(state),
+                                C.c_void_p(stream)))
     return ctx
 
 
