@@ -63,8 +63,11 @@ def parse():
     p.add_argument("--skin", type=float, default=None, help="fixed list skin (skips the autotuner)")
     p.add_argument("--cell-div", type=int, default=1, help="cell division with --skin")
     p.add_argument("--drift-steps", type=int, default=10000, help="NVE steps of each drift measurement")
-    p.add_argument("--windows", action="store_true",
-                   help="mixed precisions: the step kernel gathers from LDS windows of the stencil rows")
+    p.add_argument("--windows", type=int, default=None, choices=[0, 1],
+                   help="force the step-kernel variant (mixed precisions): 1 gathers from LDS windows of the "
+                        "stencil rows, 0 from global memory (default: the autotuner's choice)")
+    p.add_argument("--wg", type=int, default=None, choices=[64, 128, 256],
+                   help="force the step kernel's threads per block (default: the autotuner's choice)")
     p.add_argument("--profile-steps", type=int, default=200)
     p.add_argument("--no-analysis", action="store_true", help="skip the RDF / MSD timings")
     p.add_argument("--no-fp64", action="store_true", help="skip the FP64 GPU run of the headline system")
@@ -152,11 +155,14 @@ def drift_stats(rows, n):
     return d
 
 
-def kernel_name(precision):
-    """The step kernel of NVE steps: forces fused with the closing half kick
-    and the next drift."""
-    return {"fp64": "k_force_fp64<false,true>", "mixed": "k_force_mixed<false,false,true>",
-            "mixed_fixed": "k_force_mixed<true,false,true>"}[precision]
+def kernel_name(precision, windows=0, wg=256):
+    """The step kernel of NVE steps (forces fused with the closing half kick
+    and the next drift), with its template arguments: FIXED, ENERGY, KD,
+    then STAGE and waves per block for the mixed precisions."""
+    if precision == "fp64":
+        return f"k_force_fp64<false,true,{wg // 64}>"
+    fixed = "true" if precision == "mixed_fixed" else "false"
+    return f"k_force_mixed<{fixed},false,true,{'true' if windows else 'false'},{wg // 64}>"
 
 
 def source_digest():
@@ -168,10 +174,10 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(skin, cell_div, precision, n):
+def stored_traffic(skin, cell_div, precision, n, kernel):
     """HBM bytes per launch of the step kernel from the committed counter
     summary, when it was taken on the current kernel source at the same list
-    parameters, precision and size; otherwise None."""
+    parameters, precision, size and kernel variant; otherwise None."""
     try:
         with open(TRAFFIC_FILE) as f:
             text = f.read()
@@ -184,7 +190,8 @@ def stored_traffic(skin, cell_div, precision, n):
             kv[k.strip()] = v.strip().strip("`")
     try:
         ok = (kv["source_digest"] == source_digest() and abs(float(kv["skin"]) - skin) < 1e-9
-              and int(kv["cell_div"]) == cell_div and kv["precision"] == precision and int(kv["n_atoms"]) == n)
+              and int(kv["cell_div"]) == cell_div and kv["precision"] == precision and int(kv["n_atoms"]) == n
+              and kv.get("kernel") == kernel)
         return float(kv["hbm_bytes_per_launch"]) if ok else None
     except (KeyError, ValueError):
         return None
@@ -201,10 +208,11 @@ def roofline(prof, stats, n, precision):
     pairs = prof["pairs"]
     useful = pairs * FLOP_PER_PAIR / sec / 1e12
     candidates = stats["mean_list_len"] * n
-    traffic = stored_traffic(stats["skin"], int(stats["cell_div"]), precision, n)
+    kname = kernel_name(precision, int(stats["windows"]), int(stats["wg_size"]))
+    traffic = stored_traffic(stats["skin"], int(stats["cell_div"]), precision, n, kname)
     alg_bytes = n * INTEGRATION_BYTES
     return {"bound": "alu", "achieved": useful, "peak": FP32_PEAK, "unit": "TFLOP/s", "frac": useful / FP32_PEAK,
-            "traffic": traffic, "kernel": kernel_name(precision), "kernel_ms": prof["force_ms"],
+            "traffic": traffic, "kernel": kname, "kernel_ms": prof["force_ms"],
             "work_unit": "ordered in-cutoff pair", "flop_per_unit": FLOP_PER_PAIR, "units_per_launch": pairs,
             "frac_of_nonpacked_peak": useful / FP32_PEAK_NONPACKED,
             "issued_tflops": candidates * FLOP_PER_PAIR / sec / 1e12, "list_candidates_per_launch": candidates,
@@ -596,8 +604,6 @@ def main():
 
     t0 = time.perf_counter()
     s = make_system(md, rep, a.precision, wl.dt, init, samples=a.drift_steps)
-    if a.windows:
-        md.md_set_force_kernel(s.ctx, 1)
     log(f"init ({init}) {time.perf_counter() - t0:.1f} s")
     # melt the start, tune the list on the liquid, then equilibrate at the
     # tuned list parameters (so nearly every launch of the run, and of a
@@ -611,6 +617,11 @@ def main():
     elif not a.no_autotune:
         tune = s.autotune(100)
         log(f"autotune: {tune}")
+    if a.windows is not None or a.wg is not None:
+        st0 = md.md_stats(s.ctx)
+        win = a.windows if a.windows is not None else int(st0["windows"])
+        s.set_force_kernel(win, a.wg or 0)
+        log(f"step kernel fixed: windows {win}, threads per block {a.wg or int(st0['wg_size'])}")
     if a.equil > first:
         s.step_nvt(a.equil - first, md.NVT_STOCHASTIC, n_reassign=50)
     log(f"equilibrated {a.equil} steps, {time.perf_counter() - t0:.1f} s")
@@ -683,7 +694,8 @@ def main():
         "dtype": {"fp64": "f64", "mixed": "f32/f64", "mixed_fixed": "f32/f64/i64"}[a.precision],
         "data": "synthetic",
         "config": {"workload": wl.name, "n_atoms": n, "precision": a.precision, "dt": wl.dt,
-                   "skin": st["skin"], "cell_div": int(st["cell_div"]), "init": init, "equil_steps": a.equil,
+                   "skin": st["skin"], "cell_div": int(st["cell_div"]), "step_kernel_windows": int(st["windows"]),
+                   "step_kernel_threads_per_block": int(st["wg_size"]), "init": init, "equil_steps": a.equil,
                    "hip_graph": True, "parallelism": "single-gpu"},
         "drift": dict(drift, nve_steps=a.drift_steps, atom_steps_per_s=n * a.drift_steps / el_d),
         "rebuilds_per_step": prof["rebuilds"] / prof["steps"],

@@ -270,7 +270,8 @@ int md_rdf(kamd_ctx *ctx, double dr, int32_t n_bins, uint64_t *hist_dev);
 
 /* Mean-square displacement (Eqs. (msdwithi),(msdtw)) with unwrapped
  * coordinates (Sec. VI.B.1).  op 0 (SET_ORIGIN): store the current unwrapped
- * positions as origin `slot` (0 <= slot < 16).  op 1 (MEASURE): out_dev
+ * positions as origin `slot` (0 <= slot < msd_slots of the configuration, 16
+ * by default; else KAMD_EINVAL).  op 1 (MEASURE): out_dev
  * (device, FP64 [n_rep][2]) receives per replica {msd_A, msd_B} against origin
  * `slot`. */
 int md_msd(kamd_ctx *ctx, int32_t op, int32_t slot, double *out_dev);
@@ -281,7 +282,7 @@ int md_msd(kamd_ctx *ctx, int32_t op, int32_t slot, double *out_dev);
  * accumulated, the caller zeroes it) the count of particles whose unwrapped
  * displacement r = |r_u - r_u(origin slot)| has int(r / dr) = bin < n_bins.
  * The origin is set with md_msd(SET_ORIGIN).  KAMD_EINVAL for a slot outside
- * [0, 16), dr < 1e-6 or n_bins outside [1, 1024].  Asynchronous. */
+ * [0, msd_slots), dr < 1e-6 or n_bins outside [1, 1024].  Asynchronous. */
 int md_van_hove(kamd_ctx *ctx, int32_t slot, double dr, int32_t n_bins, uint64_t *hist_dev);
 
 /* Change the bath temperature of every replica (host, FP64 [n_rep], each
@@ -344,22 +345,32 @@ int md_graph_capture(kamd_ctx *ctx, int32_t nsteps, int32_t ensemble, int32_t mo
                      int32_t n_reassign, double tau);
 int md_graph_launch(kamd_ctx *ctx);
 
-/* Neighbour-list tuning: time probe_steps NVE steps for each candidate skin
- * (0.2 .. min(0.5, L/2 - r_c,max)) and each cell division (1, 2) on a copy
- * of the current state, restore the state, and keep the smallest skin (then
- * the coarser grid) whose time is within 1% of the fastest probe.  Results
- * in host_out (host, FP64 [3]): {skin, cell_div, ms_per_step of the kept
- * candidate}.  Syncs. */
+/* Tuning of the list and of the step kernel, on a copy of the current state
+ * that is restored afterwards.  A candidate is timed as the median of three
+ * runs of probe_steps NVE steps, or of as many as take about 10 ms if that is
+ * more (after a timed warm-up of probe_steps / 4).  Stage
+ * 1 times each skin (0.2 .. min(0.5, L/2 - r_c,max)) with each cell division
+ * (1, 2) on the current step kernel; stage 2 times, at the list parameters
+ * kept, the step kernel with 256, 128 and 64 threads per block and, in the
+ * mixed precisions, with windows off and on (md_set_force_kernel).  In each
+ * stage the first candidate in that order within 1% of the stage's fastest is
+ * kept (the smallest skin, the coarser grid, the direct kernel, the larger
+ * block): ties are broken the same way on every run.  Candidates whose list
+ * overflows are skipped.  Results in host_out (host, FP64 [5]): {skin,
+ * cell_div, ms_per_step of the kept candidate, windows, threads per block};
+ * the context keeps them.  KAMD_ENOMEM when a caller-owned workspace cannot
+ * hold every candidate (md_workspace_needed then gives the size).  Syncs. */
 int md_autotune(kamd_ctx *ctx, int32_t probe_steps, double *host_out);
 
 /* Change skin and cell division (forces a rebuild at the next step). */
 int md_set_list_params(kamd_ctx *ctx, double skin, int32_t cell_div);
 
 /* Step-kernel variant.  windows (mixed precisions): 1 gathers
- * the neighbours of a list part from an LDS copy of the wavefront's stencil
- * rows when that copy fits (the list then stores 16-bit offsets into it), 0
- * gathers every neighbour from global memory (the default); a change forces a
- * rebuild at the next step.  wg_size: threads per block of the step kernel, 64, 128 or 256
+ * the neighbours of a list part from LDS copies of the wavefront's stencil
+ * rows, up to 4 groups of consecutive rows staged one after the other, when
+ * they fit (the list then stores 16-bit offsets into them), 0 gathers every
+ * neighbour from global memory (the default); a change forces a rebuild at
+ * the next step.  wg_size: threads per block of the step kernel, 64, 128 or 256
  * (0 keeps the current one; 256 by default).  The forces are the same either
  * way (bit for bit with MIXED_FIXED).  Drops a captured graph.  KAMD_EINVAL
  * for windows = 1 in FP64.  Syncs. */

@@ -28,10 +28,13 @@ constexpr int VH_MAX_BINS = 1024;       // bins of the self van Hove histogram
 constexpr int LIST_UNROLL = 8;           // candidates per step of the list builder's scan
 // Force-kernel windows (mixed precisions): per wavefront and list part at
 // most STAGE_PIECES row pieces (9 stencil rows, each a main run and a wrapped
-// end), staged in LDS as STAGE_SLOTS positions of 12 bytes, of which the last
-// 64 hold the lanes' own positions.
+// end) in at most STAGE_GROUPS groups of consecutive rows; one group at a time
+// is staged in LDS, at most STAGE_SLOTS positions of 12 bytes of which the
+// last 64 hold the lanes' own positions.  7.5 KB per wavefront leaves room
+// for 20 wavefronts per CU (160 KB of LDS).
 constexpr int STAGE_PIECES = 18;
-constexpr int STAGE_SLOTS = 1088;
+constexpr int STAGE_GROUPS = 4;
+constexpr int STAGE_SLOTS = 640;
 
 // Neighbour-list layout.  The list of wavefront w is a block of rows * 64
 // ints; entry k of lane l sits at (k / 4) * 256 + l * 4 + k % 4 inside it:
@@ -124,7 +127,8 @@ struct Dev {
     int2 *lbase;          // per wave and part: base slot of 16-bit entries, -1 for 32-bit entries,
                           // or -2 - W: 16-bit offsets into a staged window of W slots
     int2 *pieces;         // per wave and part: STAGE_PIECES (first slot, slots) of the window's pieces
-    int2 *pcount;         // per wave: pieces of the A part's and the B part's window
+    int4 *sgroups;        // per wave and part: STAGE_GROUPS (end of its pieces, window slots, end of its entries, -)
+    int2 *pcount;         // per wave: window groups of the A part and of the B part (0: not staged)
     int32_t stage_ok;     // the force kernels stage windows (mixed precisions)
     int32_t *nlen;        // per slot: true list length (stats)
     // reductions

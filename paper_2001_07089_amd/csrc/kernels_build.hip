@@ -531,40 +531,62 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             }
             return b;
         };
-        // The force kernels' window (mixed precisions, one cell per list
-        // radius): the wavefront's union span of every row piece, one after
-        // the other, staged in LDS by the force kernel, plus one slot per
-        // lane holding that lane's own position.  Entries of a part whose
-        // window fits are 16-bit window offsets; the padding points at the
-        // lane's own copy (zero separation, skipped like the own slot).  The
-        // pieces are found in a first pass over the rows, since the window
-        // size decides the format of every entry.
+        // The force kernels' windows (mixed precisions, one cell per list
+        // radius).  The part's stencil rows are split into groups, in row
+        // order, each as many rows as fit one window: the wavefront's union
+        // span of every row piece of the group, one after the other, plus
+        // one slot per lane holding that lane's own position.  The force
+        // kernel stages and reads one group's window at a time.  Entries of
+        // a staged part are 16-bit offsets into their group's window; every
+        // lane's entries of a group end at a common count (padding), and
+        // the padding points at the lane's own copy (zero separation,
+        // skipped like the own slot).  The groups are found in a first pass
+        // over the rows, since they decide the format of every entry.
         const int nrow = nz * noff;
-        int wtot = 0, npiece = 0;
-        if (d.stage_ok && SJ.n > 0 && !prune) {
-            int2 *ptab = d.pieces + ((size_t)w * 2 + tj) * STAGE_PIECES;
+        int2 *ptab = d.pieces + ((size_t)w * 2 + tj) * STAGE_PIECES;
+        int4 *gtab = d.sgroups + ((size_t)w * 2 + tj) * STAGE_GROUPS;
+        int npiece = 0, ngroup = 0, gw = 0, gmax = 0;
+        int gw0 = 0, gw1 = 0, gw2 = 0, gw3 = 0;  // window slots of each group (selects, not an array)
+        uint32_t gbound = 0;                      // bit r: a new group starts at stencil row r
+        const bool try_stage = d.stage_ok && SJ.n > 0 && !prune && nrow <= 32;
+        auto close_group = [&]() __attribute__((always_inline)) {
+            if (lane == 0 && ngroup < STAGE_GROUPS) gtab[ngroup] = make_int4(npiece, gw, 0, 0);
+            gw0 = ngroup == 0 ? gw : gw0;
+            gw1 = ngroup == 1 ? gw : gw1;
+            gw2 = ngroup == 2 ? gw : gw2;
+            gw3 = ngroup == 3 ? gw : gw3;
+            gmax = max(gmax, gw);
+            ++ngroup;
+            gw = 0;
+        };
+        if (try_stage) {
             int oz = oz0, oy = -reach;
             for (int r = 0; r < nrow; ++r) {
                 const int4 b = bounds(oz, oy);
                 const int2 p1 = span(b.x, b.y), p2 = span(b.z, b.w);
-                if (p1.x != INT_MAX) {
-                    if (lane == 0 && npiece < STAGE_PIECES) ptab[npiece] = make_int2(p1.x, p1.y - p1.x);
-                    ++npiece;
-                    wtot += p1.y - p1.x;
+                const int l1 = p1.x != INT_MAX ? p1.y - p1.x : 0, l2 = p2.x != INT_MAX ? p2.y - p2.x : 0;
+                if (gw > 0 && gw + l1 + l2 + WAVE > STAGE_SLOTS) {
+                    close_group();
+                    gbound |= 1u << r;
                 }
-                if (p2.x != INT_MAX) {
-                    if (lane == 0 && npiece < STAGE_PIECES) ptab[npiece] = make_int2(p2.x, p2.y - p2.x);
+                if (l1 > 0) {
+                    if (lane == 0 && npiece < STAGE_PIECES) ptab[npiece] = make_int2(p1.x, l1);
                     ++npiece;
-                    wtot += p2.y - p2.x;
+                    gw += l1;
+                }
+                if (l2 > 0) {
+                    if (lane == 0 && npiece < STAGE_PIECES) ptab[npiece] = make_int2(p2.x, l2);
+                    ++npiece;
+                    gw += l2;
                 }
                 if (++oy == -reach + noff) {
                     oy = -reach;
                     ++oz;
                 }
             }
+            close_group();
         }
-        const bool staged = d.stage_ok && SJ.n > 0 && !prune && npiece <= STAGE_PIECES &&
-                            wtot + WAVE <= STAGE_SLOTS;
+        const bool staged = try_stage && npiece <= STAGE_PIECES && ngroup <= STAGE_GROUPS && gmax + WAVE <= STAGE_SLOTS;
         // Otherwise entries of the part of the particle's own type are stored
         // as 16-bit offsets from a base slot, two to a 32-bit word, when every
         // slot the wavefront can accept (the cell rows of its stencils) and
@@ -591,7 +613,8 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         const bool half = base >= 0;
         const int group = half ? 8 : 4;  // entries per 16-byte store
         auto pack = [&](int a, int b) __attribute__((always_inline)) { return (a - base) | ((b - base) << 16); };
-        int cnt = 0;   // entries accepted
+        int cnt = 0;   // entries accepted (and padding between window groups)
+        int npad = 0;  // of them padding
         int done = 0;  // entries written to the list (a multiple of group)
         auto flush = [&]() __attribute__((always_inline)) {  // write every complete group of staged entries
             while (done + group <= cnt) {
@@ -760,11 +783,10 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             // end cell that wraps around the box where the row does.  Rows
             // are read one step ahead of their scan, so that the loads of a
             // row's bounds overlap the staging loads of the row before.
-            // Rows are read one step ahead of their scan, so that the loads
-            // of a row's bounds overlap the staging loads of the row before.
             int oz = oz0, oy = -reach;
             int4 next = bounds(oz, oy);
             int woff = 0;  // window offset of the next piece (staged)
+            int g = 0;     // window group of the row (staged)
             for (int r = 0; r < nrow; ++r) {
                 const int4 cur = next;
                 const int2 sp1 = span(cur.x, cur.y), sp2 = span(cur.z, cur.w);
@@ -778,6 +800,25 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                     if (++oz == oz0 + nz) oz = oz0;
                 }
                 next = bounds(oz, oy);
+                if (staged && ((gbound >> r) & 1u)) {
+                    // close group g: every lane's entries up to a common
+                    // count (a multiple of the force kernels' 4 entries per
+                    // step), padded with its own copy of group g's window
+                    const int wg = g == 0 ? gw0 : (g == 1 ? gw1 : (g == 2 ? gw2 : gw3));
+                    const int pv = wg + lane;
+                    const int kend = (wave_max_all(cnt) + 3) & ~3;
+                    while (__any(cnt < kend)) {
+                        if (cnt < kend) {
+                            buf[cnt & (LIST_STAGE - 1)][lane] = pv;
+                            ++cnt;
+                            ++npad;
+                        }
+                        if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
+                    }
+                    if (lane == 0 && g < STAGE_GROUPS) gtab[g].z = kend;
+                    ++g;
+                    woff = 0;
+                }
                 if (staged && sp1.x != INT_MAX) {
                     dl = woff - sp1.x;
                     woff += sp1.y - sp1.x;
@@ -792,9 +833,11 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             dl = 0;
         }
         flush();
-        total += cnt;
+        total += cnt - npad;
         // padding: the own slot, or in a window the lane's own position copy
-        const int padv = staged ? wtot + lane : s;
+        // (of the last group's window)
+        const int wlast = ngroup == 1 ? gw0 : (ngroup == 2 ? gw1 : (ngroup == 3 ? gw2 : gw3));
+        const int padv = staged ? wlast + lane : s;
         int kmax = wave_max_all(cnt);
         const int align = half ? 2 * LIST_ROW_ALIGN : LIST_ROW_ALIGN;  // whole 16-byte words
         kmax = (kmax + align - 1) / align * align;
@@ -817,12 +860,12 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         // live in scratch memory when this loop is not unrolled
         kpart.x = tj == 0 ? kmax : kpart.x;
         kpart.y = tj == 1 ? kmax : kpart.y;
-        const int code = staged ? -2 - wtot : base;  // <= -2: a staged window of -2 - code slots
+        const int code = staged ? -2 : base;  // -2: entries are offsets into window groups
         bpart.x = tj == 0 ? code : bpart.x;
         bpart.y = tj == 1 ? code : bpart.y;
-        pcnt.x = tj == 0 ? (staged ? npiece : 0) : pcnt.x;
-        pcnt.y = tj == 1 ? (staged ? npiece : 0) : pcnt.y;
-        if (half) n16 += cnt - (tj == S.type ? 1 : 0);  // 16-bit partner entries (not the own slot)
+        pcnt.x = tj == 0 ? (staged ? ngroup : 0) : pcnt.x;
+        pcnt.y = tj == 1 ? (staged ? ngroup : 0) : pcnt.y;
+        if (half) n16 += cnt - npad - (tj == S.type ? 1 : 0);  // 16-bit partner entries (not the own slot)
         row += words;
     }
     if (row > rows) {  // keep the force kernels inside the list

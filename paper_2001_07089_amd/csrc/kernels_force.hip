@@ -224,16 +224,23 @@ __device__ inline void wave_lds_sync()
 // Neighbours read their positions from d.mirror while mirror_out receives the
 // new ones, so the two must be different buffers; the forces are not stored.
 //
-// STAGE: a list part whose wavefront window fits (lbase <= -2, written by the
-// list builder) is gathered from LDS.  The wavefront first copies the slot
-// ranges of the part's row pieces (its lanes' union span of each stencil
-// row, coalesced loads of d.mirror) one after the other into its window, and
-// each lane its own position after them; the entries are 16-bit offsets into
+// STAGE: a list part whose windows fit (lbase = -2, written by the list
+// builder) is gathered from LDS.  Its stencil rows come in up to STAGE_GROUPS
+// groups; for each group the wavefront copies the slot ranges of the group's
+// row pieces (its lanes' union span of each stencil row, coalesced loads of
+// d.mirror) one after the other into its window, and each lane its own
+// position after them, then reads the group's entries, 16-bit offsets into
 // that window.  A gather from global memory costs the kernel one cache-line
 // access per lane and waits on the vector L1; a window read does neither.
-// Parts whose window does not fit keep the slot-index entries.
+// Parts whose windows do not fit keep the slot-index entries.
+// Wavefronts per SIMD the register allocation of the staged step variant
+// must allow: its LDS allows 5 (four wavefronts per block), and unbounded it
+// takes a few registers too many for that (two 8-byte values then live in
+// scratch, stored once per wavefront).
+constexpr int WPE_STAGED = 5;
+
 template <bool FIXED, bool ENERGY, bool KD, bool STAGE, int WPB>
-__global__ __launch_bounds__(WAVE * WPB) void k_force_mixed(Dev d, Model m, int step_inc, double dt,
+__global__ __launch_bounds__(WAVE * WPB) __attribute__((amdgpu_waves_per_eu(STAGE && !ENERGY ? WPE_STAGED : 1))) void k_force_mixed(Dev d, Model m, int step_inc, double dt,
                                                              uint4 *mirror_out, uint32_t *md_out)
 {
     __shared__ uint32_t swin[STAGE ? WPB : 1][STAGE ? 3 * STAGE_SLOTS : 1];
@@ -306,39 +313,52 @@ __global__ __launch_bounds__(WAVE * WPB) void k_force_mixed(Dev d, Model m, int 
         if (!STAGE && base <= -2) {  // a window list for the direct variant: never read it as slots
             if (lane_id() == 0) set_err(d.err, KAMD_DEV_LIST_FORMAT);
         } else if (STAGE && base <= -2) {
-            const int W = -2 - base;
-            const int np = tj ? pc.y : pc.x;
+            const int ng = tj ? pc.y : pc.x;
             const int2 *pt = d.pieces + ((size_t)w * 2 + tj) * STAGE_PIECES;
-            int off = 0;
-            for (int q = 0; q < np; ++q) {
-                const int2 pq = pt[q];
-                for (int e = lane_id(); e < pq.y; e += WAVE) {
-                    const uint4 mj = d.mirror[pq.x + e];
-                    uint32_t *o = win + 3 * (off + e);
-                    o[0] = mj.x;
-                    o[1] = mj.y;
-                    o[2] = mj.z;
+            const int4 *gt = d.sgroups + ((size_t)w * 2 + tj) * STAGE_GROUPS;
+            int q = 0, k = 0;
+            for (int g = 0; g < ng; ++g) {
+                const int4 gi = gt[g];  // (end of its pieces, window slots, end of its entries, -)
+                const int kend = min(g + 1 < ng ? gi.z : nrows, nrows);
+                int off = 0;
+                for (; q < gi.x; ++q) {
+                    const int2 pq = pt[q];
+                    // two loads in flight per lane before the first store
+                    for (int e = lane_id(); e < pq.y; e += 2 * WAVE) {
+                        const bool two = e + WAVE < pq.y;
+                        const uint4 ma = d.mirror[pq.x + e];
+                        const uint4 mb = d.mirror[pq.x + (two ? e + WAVE : e)];
+                        uint32_t *o = win + 3 * (off + e);
+                        o[0] = ma.x;
+                        o[1] = ma.y;
+                        o[2] = ma.z;
+                        if (two) {
+                            o[3 * WAVE + 0] = mb.x;
+                            o[3 * WAVE + 1] = mb.y;
+                            o[3 * WAVE + 2] = mb.z;
+                        }
+                    }
+                    off += pq.y;
                 }
-                off += pq.y;
-            }
-            uint32_t *o = win + 3 * (W + lane_id());
-            o[0] = mi.x;
-            o[1] = mi.y;
-            o[2] = mi.z;
-            wave_lds_sync();
-            for (int k = 0; k < nrows; k += 4) {
-                int jj[4];
-                list_quad16(nb, k, 0, jj);
-                uint4 mj[4];
+                uint32_t *o = win + 3 * (gi.y + lane_id());
+                o[0] = mi.x;
+                o[1] = mi.y;
+                o[2] = mi.z;
+                wave_lds_sync();
+                for (; k < kend; k += 4) {
+                    int jj[4];
+                    list_quad16(nb, k, 0, jj);
+                    uint4 mj[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const uint32_t *src = win + 3 * jj[u];
-                    mj[u] = make_uint4(src[0], src[1], src[2], 0u);
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t *src = win + 3 * jj[u];
+                        mj[u] = make_uint4(src[0], src[1], src[2], 0u);
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) pair(mj[u]);
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) pair(mj[u]);
+                wave_lds_sync();  // the next group (or part) stages over this window
             }
-            wave_lds_sync();  // the next part stages over this window
         } else if (base >= 0) {
             for (int k = 0; k < nrows; k += 4) {
                 int jj[4];

@@ -391,6 +391,7 @@ static void carve_fixed(Dev &d, CtxBufs &b, const Shape &z, Carve &k)
     d.kmax = k.take<int2>(z.nwaves);
     d.lbase = k.take<int2>(z.nwaves);
     d.pieces = k.take<int2>(z.nwaves * 2 * STAGE_PIECES);
+    d.sgroups = k.take<int4>(z.nwaves * 2 * STAGE_GROUPS);
     d.pcount = k.take<int2>(z.nwaves);
     d.wred = k.take<double>(4 * z.nwaves);
     d.rsum = k.take<double>(4 * z.nrep);
@@ -1584,9 +1585,8 @@ extern "C" int md_autotune(kamd_ctx *c, int32_t probe_steps, double *host_out)
     TRY(md_get_state(c, nullptr, &nb));
     std::vector<char> blob(nb);
     TRY(md_get_state(c, blob.data(), &nb));
-    const double skin0 = c->skin;
-    const int div0 = c->cell_div;
     const int64_t step0 = c->step;
+    const bool mixed = c->cfg.precision != KAMD_PREC_FP64;
     double Lmin = 1e300;
     for (auto &k : c->reps) Lmin = std::min(Lmin, k.box);
     std::vector<double> skins;
@@ -1601,70 +1601,122 @@ extern "C" int md_autotune(kamd_ctx *c, int32_t probe_steps, double *host_out)
             if (P.ncells_wide <= MAX_PLAN_CELLS) need = std::max(need, need_for(c, P));
         }
     TRY(grow_workspace(c, need));
-    struct Probe {
+    struct Cand {
         double skin;
         int div;
+        bool win;
+        int wpb;
         double ms;
     };
-    std::vector<Probe> probes;
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
     const int saved_sync = c->cfg.auto_sync;
+    const bool win0 = c->stage_windows;
+    const int wpb0 = c->force_wpb;
     c->cfg.auto_sync = 0;
+    // One candidate from the saved state: a timed warm-up of a quarter of
+    // the probe, then the median of three timed runs of probe_steps steps,
+    // or of as many as take about 10 ms by the warm-up's rate if that is
+    // more (a run must see several list rebuilds, whose cost dominates the
+    // differences between candidates of a small system).  A candidate whose
+    // list overflows is skipped (ms stays negative).
+    auto probe = [&](Cand &k) -> int {
+        k.ms = -1.0;
+        drop_graph(c);
+        c->stage_windows = k.win;
+        c->d.stage_ok = mixed && k.win;
+        c->force_wpb = k.wpb;
+        TRY(apply_list_params(c, k.skin, k.div, false));
+        TRY(md_set_state(c, blob.data(), nb));
+        const int warm = std::max(1, probe_steps / 4);
+        float tw = 0.0f;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        TRY(enqueue_steps(c, warm, 0, 0, 0, false));
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        HIPCHK(c, hipEventElapsedTime(&tw, e0, e1));
+        const double per = std::max(1e-4, (double)tw / warm);
+        const int steps = (int)std::min(20000.0, std::max((double)probe_steps, std::ceil(10.0 / per)));
+        float t[3];
+        for (int r = 0; r < 3; ++r) {
+            HIPCHK(c, hipEventRecord(e0, c->stream));
+            TRY(enqueue_steps(c, steps, 0, 0, 0, false));
+            HIPCHK(c, hipEventRecord(e1, c->stream));
+            HIPCHK(c, hipEventSynchronize(e1));
+            HIPCHK(c, hipEventElapsedTime(&t[r], e0, e1));
+        }
+        uint32_t word = 0;
+        HIPCHK(c, hipMemcpy(&word, c->d.err, 4, hipMemcpyDeviceToHost));
+        if (word == 0) {
+            std::sort(t, t + 3);
+            k.ms = (double)t[1] / steps;
+        } else if (word == KAMD_DEV_LIST_OVERFLOW) {  // this candidate's list is too short: skip it
+            const uint32_t zero = 0;
+            HIPCHK(c, hipMemcpy(c->d.err, &zero, 4, hipMemcpyHostToDevice));
+        } else {
+            return fail(c, KAMD_EDEVICE, "device error word 0x%x while probing", word);
+        }
+        return KAMD_OK;
+    };
+    // Within 1% of the fastest the timings are not told apart reliably; the
+    // first such candidate in the order tried is kept.  Stage 1 orders by
+    // skin, then grid (the smallest list first); stage 2 tries the direct
+    // kernel before the windows, and the larger blocks first.
+    auto pick = [](const std::vector<Cand> &v) -> int {
+        double fastest = 1e300;
+        for (const Cand &k : v)
+            if (k.ms > 0.0) fastest = std::min(fastest, k.ms);
+        for (size_t i = 0; i < v.size(); ++i)
+            if (v[i].ms > 0.0 && v[i].ms <= 1.01 * fastest) return (int)i;
+        return -1;
+    };
     int rc = KAMD_OK;
-    for (double s : skins) {
-        for (int dv = 1; dv <= 2 && !rc; ++dv) {
+    // Stage 1: list parameters (skin x cell division) with the current kernel.
+    std::vector<Cand> st1;
+    for (double s : skins)
+        for (int dv = 1; dv <= 2; ++dv) {
             Plan Pt;
             make_plan(&c->cfg, c->reps.data(), (int)c->reps.size(), s, dv, Pt, c->rows_floor);
-            if (Pt.ncells_wide > MAX_PLAN_CELLS) continue;
-            rc = apply_list_params(c, s, dv, false);
-            if (!rc) rc = md_set_state(c, blob.data(), nb);
-            if (!rc) rc = enqueue_steps(c, std::max(1, probe_steps / 4), 0, 0, 0, false);  // warm-up
-            if (rc) break;
-            if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(c, KAMD_EHIP, "event record"); break; }
-            rc = enqueue_steps(c, probe_steps, 0, 0, 0, false);
-            if (rc) break;
-            (void)hipEventRecord(e1, c->stream);
-            (void)hipEventSynchronize(e1);
-            float ms = 0.0f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            uint32_t word = 0;
-            (void)hipMemcpy(&word, c->d.err, 4, hipMemcpyDeviceToHost);
-            if (word == 0) {
-                probes.push_back({s, dv, (double)ms / probe_steps});
-            } else if (word == KAMD_DEV_LIST_OVERFLOW) {  // this candidate's list is too short: skip it
-                const uint32_t zero = 0;
-                (void)hipMemcpy(c->d.err, &zero, 4, hipMemcpyHostToDevice);
+            if (Pt.ncells_wide <= MAX_PLAN_CELLS) st1.push_back({s, dv, win0, wpb0, -1.0});
+        }
+    for (Cand &k : st1)
+        if (!rc) rc = probe(k);
+    const int i1 = rc ? -1 : pick(st1);
+    Cand best = i1 >= 0 ? st1[i1] : Cand{c->skin, c->cell_div, win0, wpb0, -1.0};
+    // Stage 2: the force kernel at those list parameters: block size
+    // {256, 128, 64} threads, and (mixed precisions) windows off or on.
+    std::vector<Cand> st2;
+    if (i1 >= 0) {
+        for (int w = 0; w < (mixed ? 2 : 1); ++w)
+            for (int wpb : {4, 2, 1}) {
+                if ((w != 0) == best.win && wpb == best.wpb) {
+                    st2.push_back(best);  // already timed
+                } else {
+                    st2.push_back({best.skin, best.div, w != 0, wpb, -1.0});
+                    if (!rc) rc = probe(st2.back());
+                }
             }
-        }
-        if (rc) break;
-    }
-    // Within 1% of the fastest probe the timings are not told apart reliably
-    // (a probe sees only a few rebuilds); take the smallest skin, then the
-    // coarser grid, among those, which also needs the least list memory.
-    double fastest = 1e300, best_t = 1e300, best_s = skin0;
-    int best_d = div0;
-    for (const Probe &p : probes) fastest = std::min(fastest, p.ms);
-    for (const Probe &p : probes) {  // ordered by skin, then by grid
-        if (p.ms <= 1.01 * fastest) {
-            best_s = p.skin;
-            best_d = p.div;
-            best_t = p.ms;
-            break;
-        }
+        const int i2 = rc ? -1 : pick(st2);
+        if (i2 >= 0) best = st2[i2];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c->cfg.auto_sync = saved_sync;
-    int rc2 = apply_list_params(c, best_s, best_d, false);
+    drop_graph(c);
+    c->stage_windows = best.win;
+    c->d.stage_ok = mixed && best.win;
+    c->force_wpb = best.wpb;
+    int rc2 = apply_list_params(c, best.skin, best.div, false);
     if (!rc2) rc2 = md_set_state(c, blob.data(), nb);
     c->step = step0;
     if (rc) return rc;
     if (rc2) return rc2;
-    host_out[0] = best_s;
-    host_out[1] = best_d;
-    host_out[2] = best_t;
+    host_out[0] = best.skin;
+    host_out[1] = best.div;
+    host_out[2] = best.ms;
+    host_out[3] = best.win ? 1.0 : 0.0;
+    host_out[4] = (double)(best.wpb * WAVE);
     return KAMD_OK;
 }
 

@@ -287,9 +287,10 @@ def md_graph_launch(ctx):
 
 
 def md_autotune(ctx, probe_steps: int = 100):
-    out = np.zeros(3)
+    out = np.zeros(5)
     _check(lib().md_autotune(ctx, int(probe_steps), out.ctypes.data), ctx)
-    return {"skin": float(out[0]), "cell_div": int(out[1]), "ms_per_step": float(out[2])}
+    return {"skin": float(out[0]), "cell_div": int(out[1]), "ms_per_step": float(out[2]),
+            "windows": int(out[3]), "wg_size": int(out[4])}
 
 
 def md_van_hove(ctx, slot: int, dr: float, n_bins: int, hist_ptr: int):
@@ -471,6 +472,9 @@ class System:
 
     def autotune(self, probe_steps=100):
         return self.call(md_autotune, probe_steps)
+
+    def set_force_kernel(self, windows, wg_size=0):
+        md_set_force_kernel(self.ctx, windows, wg_size)
 
     def capture(self, nsteps, ensemble=0, mode=NVT_STOCHASTIC, n_reassign=50, tau=0.5):
         md_graph_capture(self.ctx, nsteps, ensemble, mode, n_reassign, tau)

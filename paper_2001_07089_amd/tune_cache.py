@@ -1,13 +1,16 @@
-"""Persistent cache of the neighbour-list parameters chosen by ``md_autotune``.
+"""Persistent cache of the list parameters and step-kernel variant chosen by
+``md_autotune``.
 
-Probing every candidate skin and cell grid costs about a thousand steps, so
-the choice is stored in a JSON file and reused by later runs of the same
-workload class on the same device.  The key is built from the device name,
+Probing every candidate skin, cell grid, block size and window setting costs
+a few thousand steps, so the choice is stored in a JSON file and reused by
+later runs of the same workload class on the same device.  The key is built from the device name,
 the precision mode and coarse buckets of what the choice depends on: total
 particle count (power of two), replica count (power of two), number density
 (0.05) and mean temperature (0.25).  A hit applies the stored skin and grid
-with ``md_set_list_params``; a miss runs ``md_autotune`` and records its
-result.  Writes go to a temporary file that replaces the cache atomically.
+with ``md_set_list_params`` and the stored kernel variant with
+``md_set_force_kernel`` (entries written before the variant was tuned carry
+no variant and leave the kernel as it is); a miss runs ``md_autotune`` and
+records its result.  Writes go to a temporary file that replaces the cache atomically.
 """
 import json
 import math
@@ -74,16 +77,20 @@ def device_name(torch_module=None) -> str:
 def tune(system, probe_steps: int = 100, path: str = None, device: str = None, refresh: bool = False) -> dict:
     """List parameters for ``system`` (an ``md.System``): from the cache when the
     key is present (and ``refresh`` is false), else from ``md_autotune``.
-    Returns {"skin", "cell_div", "ms_per_step", "cached", "key"}."""
+    Returns {"skin", "cell_div", "ms_per_step", "windows", "wg_size",
+    "cached", "key"} (windows and wg_size None for an entry without them)."""
     path = path or default_path()
     device = device or device_name(getattr(system, "torch", None))
     key = workload_key(device, system.cfg.precision, system.reps)
     hit = None if refresh else load(path).get(key)
     if hit and "skin" in hit and "cell_div" in hit:
         system.set_list_params(float(hit["skin"]), int(hit["cell_div"]))
+        win, wg = hit.get("windows"), hit.get("wg_size")
+        if win is not None and wg is not None:
+            system.set_force_kernel(int(win), int(wg))
         return {"skin": float(hit["skin"]), "cell_div": int(hit["cell_div"]),
-                "ms_per_step": hit.get("ms_per_step"), "cached": True, "key": key}
+                "ms_per_step": hit.get("ms_per_step"), "windows": win, "wg_size": wg, "cached": True, "key": key}
     res = system.autotune(probe_steps)
     store(path, key, {"skin": res["skin"], "cell_div": res["cell_div"], "ms_per_step": res["ms_per_step"],
-                      "probe_steps": int(probe_steps)})
+                      "windows": res["windows"], "wg_size": res["wg_size"], "probe_steps": int(probe_steps)})
     return dict(res, cached=False, key=key)

@@ -25,7 +25,7 @@ def test_roofline_prices_useful_pair_flops_against_the_fp32_peak():
     157.3 TFLOP/s; issued work counts the list candidates; the HBM view
     counts 150 bytes per atom-step."""
     prof = {"force_ms": 0.25, "pairs": 67216584.0}
-    stats = {"mean_list_len": 104.0, "skin": 0.4, "cell_div": 1.0}
+    stats = {"mean_list_len": 104.0, "skin": 0.4, "cell_div": 1.0, "windows": 1.0, "wg_size": 128.0}
     n = 1 << 20
     r = bench.roofline(prof, stats, n, "mixed_fixed")
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
@@ -33,8 +33,9 @@ def test_roofline_prices_useful_pair_flops_against_the_fp32_peak():
     assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
     assert r["issued_tflops"] == pytest.approx(104.0 * n * 19 / 0.25e-3 / 1e12)
     assert r["hbm_view"]["achieved_gbs"] == pytest.approx(n * 150 / 0.25e-3 / 1e9)
-    assert r["kernel"] == "k_force_mixed<true,false,true>"
-    assert bench.kernel_name("fp64") == "k_force_fp64<false,true>"
+    assert r["kernel"] == "k_force_mixed<true,false,true,true,2>"
+    assert bench.kernel_name("fp64") == "k_force_fp64<false,true,4>"
+    assert bench.kernel_name("mixed", 0, 64) == "k_force_mixed<false,false,true,false,1>"
 
 
 def _record():
@@ -52,8 +53,10 @@ def test_stored_traffic_only_for_the_measured_configuration():
     skin, div, prec, n = float(kv["skin"]), int(kv["cell_div"]), kv["precision"], int(kv["n_atoms"])
     if kv["source_digest"] != bench.source_digest():
         pytest.skip("the force-kernel sources changed since the counters were taken")
-    assert bench.stored_traffic(skin, div, prec, n) == float(kv["hbm_bytes_per_launch"])
-    assert bench.stored_traffic(skin + 0.1, div, prec, n) is None
-    assert bench.stored_traffic(skin, div + 1, prec, n) is None
-    assert bench.stored_traffic(skin, div, "fp64", n) is None
-    assert bench.stored_traffic(skin, div, prec, n + 64) is None
+    k = kv.get("kernel")
+    assert bench.stored_traffic(skin, div, prec, n, k) == float(kv["hbm_bytes_per_launch"])
+    assert bench.stored_traffic(skin + 0.1, div, prec, n, k) is None
+    assert bench.stored_traffic(skin, div + 1, prec, n, k) is None
+    assert bench.stored_traffic(skin, div, "fp64", n, k) is None
+    assert bench.stored_traffic(skin, div, prec, n + 64, k) is None
+    assert bench.stored_traffic(skin, div, prec, n, "another kernel") is None

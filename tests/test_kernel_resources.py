@@ -26,9 +26,24 @@ def _kernels():
     return out
 
 
+# The opt-in window variant of the mixed step kernel (template argument STAGE
+# = true, ENERGY = false) is held to the register count that its LDS use
+# allows (five wavefronts per SIMD); the compiler then keeps two 8-byte values
+# in scratch (20 bytes per lane), stored once per wavefront, outside the pair
+# loops.  The variant runs faster so than without the bound; it may use at
+# most this much.
+STAGED_STEP = re.compile(r"k_force_mixedILb[01]ELb0ELb[01]ELb1E")
+STAGED_SCRATCH_MAX = 32
+
+
 def test_no_hot_kernel_uses_scratch():
     ks = _kernels()
     hot = [k for k in ks if re.search(r"k_rb_|k_force_|k_kick|k_drift|k_rdf_|k_van_hove|k_msd_", k)]
     assert len(hot) >= 12
-    bad = {k: ks[k].get("ScratchSize") for k in hot if ks[k].get("ScratchSize", 0) != 0}
+    bad = {k: ks[k].get("ScratchSize") for k in hot
+           if ks[k].get("ScratchSize", 0) != 0 and not STAGED_STEP.search(k)}
     assert not bad, bad
+    staged = [k for k in hot if STAGED_STEP.search(k)]
+    assert staged
+    over = {k: ks[k].get("ScratchSize") for k in staged if ks[k].get("ScratchSize", 0) > STAGED_SCRATCH_MAX}
+    assert not over, over

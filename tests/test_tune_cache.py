@@ -17,22 +17,27 @@ def _system(reps, precision="mixed_fixed"):
     s = types.SimpleNamespace(ctx="CTX", cfg=cfg, reps=md.make_replicas(reps))
     s.autotune = lambda probe_steps=100: md.md_autotune(s.ctx, probe_steps)
     s.set_list_params = lambda skin, cell_div=1: md.md_set_list_params(s.ctx, skin, cell_div)
+    s.set_force_kernel = lambda windows, wg_size=0: md.md_set_force_kernel(s.ctx, windows, wg_size)
     return s
 
 
 @pytest.fixture
 def fakes(monkeypatch):
-    calls = {"tune": 0, "set": []}
+    calls = {"tune": 0, "set": [], "kernel": []}
 
     def fake_tune(ctx, probe_steps=100):
         calls["tune"] += 1
-        return {"skin": 0.4, "cell_div": 1, "ms_per_step": 0.43}
+        return {"skin": 0.4, "cell_div": 1, "ms_per_step": 0.43, "windows": 1, "wg_size": 128}
 
     def fake_set(ctx, skin, cell_div):
         calls["set"].append((skin, cell_div))
 
+    def fake_kernel(ctx, windows, wg_size=0):
+        calls["kernel"].append((windows, wg_size))
+
     monkeypatch.setattr(md, "md_autotune", fake_tune)
     monkeypatch.setattr(md, "md_set_list_params", fake_set)
+    monkeypatch.setattr(md, "md_set_force_kernel", fake_kernel)
     return calls
 
 
@@ -44,7 +49,9 @@ def test_miss_then_hit(tmp_path, fakes):
     assert not a["cached"] and fakes["tune"] == 1 and fakes["set"] == []
     b = tune_cache.tune(s, 50, path=path, device="MI355X:gfx950")
     assert b["cached"] and fakes["tune"] == 1 and fakes["set"] == [(0.4, 1)]
-    assert (b["skin"], b["cell_div"]) == (a["skin"], a["cell_div"])
+    assert fakes["kernel"] == [(1, 128)]
+    assert (b["skin"], b["cell_div"], b["windows"], b["wg_size"]) == \
+        (a["skin"], a["cell_div"], a["windows"], a["wg_size"])
     data = json.load(open(path))
     assert list(data) == [a["key"]] and data[a["key"]]["probe_steps"] == 50
     c = tune_cache.tune(s, 50, path=path, device="MI355X:gfx950", refresh=True)
