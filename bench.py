@@ -174,27 +174,40 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(skin, cell_div, precision, n, kernel):
-    """HBM bytes per launch of the step kernel from the committed counter
-    summary, when it was taken on the current kernel source at the same list
-    parameters, precision, size and kernel variant; otherwise None."""
+def traffic_records(path=None):
+    """The machine-readable records of the committed counter summary: one
+    dict per "### Record" section of "- key: value" lines."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path or TRAFFIC_FILE) as f:
             text = f.read()
     except OSError:
-        return None
-    kv = {}
+        return []
+    recs, cur = [], None
     for line in text.splitlines():
-        if line.startswith("- ") and ": " in line:
+        if line.startswith("### Record"):
+            cur = {}
+            recs.append(cur)
+        elif cur is not None and line.startswith("- ") and ": " in line:
             k, v = line[2:].split(": ", 1)
-            kv[k.strip()] = v.strip().strip("`")
-    try:
-        ok = (kv["source_digest"] == source_digest() and abs(float(kv["skin"]) - skin) < 1e-9
-              and int(kv["cell_div"]) == cell_div and kv["precision"] == precision and int(kv["n_atoms"]) == n
-              and kv.get("kernel") == kernel)
-        return float(kv["hbm_bytes_per_launch"]) if ok else None
-    except (KeyError, ValueError):
-        return None
+            cur[k.strip()] = v.strip().strip("`")
+    return recs
+
+
+def stored_traffic(skin, cell_div, precision, n, kernel):
+    """HBM bytes per launch of the step kernel from the committed counter
+    summary, when a record there was taken on the current kernel source at the
+    same list parameters, precision, size and kernel variant; otherwise None."""
+    digest = source_digest()
+    for kv in traffic_records():
+        try:
+            ok = (kv["source_digest"] == digest and abs(float(kv["skin"]) - skin) < 1e-9
+                  and int(kv["cell_div"]) == cell_div and kv["precision"] == precision
+                  and int(kv["n_atoms"]) == n and kv.get("kernel") == kernel)
+            if ok:
+                return float(kv["hbm_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def roofline(prof, stats, n, precision):

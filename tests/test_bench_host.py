@@ -38,25 +38,25 @@ def test_roofline_prices_useful_pair_flops_against_the_fp32_peak():
     assert bench.kernel_name("mixed", 0, 64) == "k_force_mixed<false,false,true,false,1>"
 
 
-def _record():
-    kv = {}
-    with open(bench.TRAFFIC_FILE) as f:
-        for line in f:
-            if line.startswith("- ") and ": " in line:
-                k, v = line[2:].split(": ", 1)
-                kv[k.strip()] = v.strip().strip("`")
-    return kv
-
-
 def test_stored_traffic_only_for_the_measured_configuration():
-    kv = _record()
+    recs = bench.traffic_records()
+    assert recs, "no record in the committed counter summary"
+    kv = recs[0]
     skin, div, prec, n = float(kv["skin"]), int(kv["cell_div"]), kv["precision"], int(kv["n_atoms"])
     if kv["source_digest"] != bench.source_digest():
         pytest.skip("the force-kernel sources changed since the counters were taken")
     k = kv.get("kernel")
     assert bench.stored_traffic(skin, div, prec, n, k) == float(kv["hbm_bytes_per_launch"])
-    assert bench.stored_traffic(skin + 0.1, div, prec, n, k) is None
+    assert bench.stored_traffic(skin + 0.01, div, prec, n, k) is None
     assert bench.stored_traffic(skin, div + 1, prec, n, k) is None
     assert bench.stored_traffic(skin, div, "fp64", n, k) is None
     assert bench.stored_traffic(skin, div, prec, n + 64, k) is None
     assert bench.stored_traffic(skin, div, prec, n, "another kernel") is None
+
+
+def test_traffic_records_parse_sections(tmp_path):
+    p = tmp_path / "t.md"
+    p.write_text("text\n- ignored: 1\n### Record A\n- skin: 0.3\n- kernel: `k<a>`\n"
+                 "### Record B\n- skin: 0.4\nprose\n- hbm_bytes_per_launch: 5\n")
+    recs = bench.traffic_records(str(p))
+    assert recs == [{"skin": "0.3", "kernel": "k<a>"}, {"skin": "0.4", "hbm_bytes_per_launch": "5"}]
