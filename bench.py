@@ -45,6 +45,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "force_kernel_hbm_traffic.md")
 TRAFFIC_SOURCES = ("paper_2001_07089_amd/csrc/kernels_force.hip", "paper_2001_07089_amd/csrc/common_dev.hpp",
                    "paper_2001_07089_amd/csrc/kamd_internal.hpp")
 SAMPLE_EVERY = 10
+# tuned picks shipped with the package (tune_cache format, keyed by device and workload class)
+TUNE_CACHE = os.path.join(ROOT, "paper_2001_07089_amd", "tuned", "autotune.json")
+TUNE = {"path": TUNE_CACHE, "refresh": False}
+
+
+def tuned(s, probe_steps):
+    """The autotuner's pick for this system: from the cache when it holds one
+    for the workload class on this device, else from md_autotune (stored)."""
+    from paper_2001_07089_amd import tune_cache
+    return tune_cache.tune(s, probe_steps, path=TUNE["path"], refresh=TUNE["refresh"])
 
 
 def log(*a):
@@ -60,6 +70,10 @@ def parse():
     p.add_argument("--precision", default="mixed_fixed", choices=["fp64", "mixed", "mixed_fixed"])
     p.add_argument("--equil", type=int, default=6000, help="stochastic-bath steps before timing")
     p.add_argument("--no-autotune", action="store_true")
+    p.add_argument("--tune-cache", default=TUNE_CACHE,
+                   help="autotuner cache: a stored pick for the workload class and device is applied as is "
+                        "(reproducible list parameters, hence trajectories); a miss runs the autotuner and stores")
+    p.add_argument("--retune", action="store_true", help="run the autotuner even where the cache holds a pick")
     p.add_argument("--skin", type=float, default=None, help="fixed list skin (skips the autotuner)")
     p.add_argument("--cell-div", type=int, default=1, help="cell division with --skin")
     p.add_argument("--drift-steps", type=int, default=10000, help="NVE steps of each drift measurement")
@@ -88,6 +102,7 @@ def parse():
                    help="only run a plain device copy of MIB MiB (5 times) and exit: the reference "
                         "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     a = p.parse_args()
+    TUNE["path"], TUNE["refresh"] = a.tune_cache, a.retune
     if a.only_headline:
         a.no_fp64 = a.no_small = a.no_medium = a.no_batch = a.no_batch_large = a.no_cpu = True
         a.no_analysis = True
@@ -395,7 +410,7 @@ def batched(md, torch, W, steps):
     log(f"batch init (rsa, {len(reps)} replicas, {wl.n_total} particles) {time.perf_counter() - t0:.1f} s")
     s.step_nvt(500, md.NVT_STOCHASTIC, n_reassign=10)
     s.step_nvt(1500, md.NVT_STOCHASTIC, n_reassign=50)
-    tune = s.autotune(60)
+    tune = tuned(s, 60)
     s.step_nve(200)
     el, rows = drift_run(s, torch, steps)
     from paper_2001_07089_amd import analysis
@@ -503,7 +518,7 @@ def planar_leg(md, torch, W, steps=1000):
                   init="lattice", auto_sync=False, dim=2, sample_every=SAMPLE_EVERY,
                   sample_capacity=ring_rows(10000))
     s.step_nvt(12000, md.NVT_STOCHASTIC, n_reassign=10)
-    tune = s.autotune(100)
+    tune = tuned(s, 100)
     s.step_nve(200)
     el = timed_graph(s, torch, steps)
     _, rows = drift_run(s, torch, 10000)
@@ -628,7 +643,7 @@ def main():
         s.set_list_params(a.skin, a.cell_div)
         log(f"list parameters fixed: skin {a.skin}, cell_div {a.cell_div}")
     elif not a.no_autotune:
-        tune = s.autotune(100)
+        tune = tuned(s, 100)
         log(f"autotune: {tune}")
     if a.windows is not None or a.wg is not None:
         st0 = md.md_stats(s.ctx)
