@@ -415,6 +415,10 @@ constexpr int LIST_STAGE = 16;
 constexpr double COARSE_MAX_BOX = 220.0;
 constexpr int LIST_WIN = 384;
 
+// STAGE: the window variant of the force kernels is on (d.stage_ok), so
+// parts whose windows fit are written in the window format; without it the
+// window code is compiled out.
+template <bool STAGE>
 __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
 {
     __shared__ int32_t stage[WAVES_PER_BLOCK][LIST_STAGE][WAVE];
@@ -548,7 +552,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         int npiece = 0, ngroup = 0, gw = 0, gmax = 0;
         int gw0 = 0, gw1 = 0, gw2 = 0, gw3 = 0;  // window slots of each group (selects, not an array)
         uint32_t gbound = 0;                      // bit r: a new group starts at stencil row r
-        const bool try_stage = d.stage_ok && SJ.n > 0 && !prune && nrow <= 32;
+        const bool try_stage = STAGE && SJ.n > 0 && !prune && nrow <= 32;
         auto close_group = [&]() __attribute__((always_inline)) {
             if (lane == 0 && ngroup < STAGE_GROUPS) gtab[ngroup] = make_int4(npiece, gw, 0, 0);
             gw0 = ngroup == 0 ? gw : gw0;
@@ -921,7 +925,10 @@ hipError_t launch_rb_sortgather(const Dev &d, hipStream_t s)
 }
 hipError_t launch_rb_list(const Dev &d, int cell_div, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rb_list, dim3(nblk_slots(d)), dim3(BLOCK), 0, s, d, cell_div);
+    if (d.stage_ok)
+        hipLaunchKernelGGL(k_rb_list<true>, dim3(nblk_slots(d)), dim3(BLOCK), 0, s, d, cell_div);
+    else
+        hipLaunchKernelGGL(k_rb_list<false>, dim3(nblk_slots(d)), dim3(BLOCK), 0, s, d, cell_div);
     return hipGetLastError();
 }
 
