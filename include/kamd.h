@@ -210,7 +210,8 @@ int md_workspace_needed(kamd_ctx *ctx, size_t *bytes);
 /* Move the context into another caller-owned workspace (device, ws_bytes >=
  * md_workspace_needed, 256-byte aligned, not the current one): the contents
  * are copied, the old block is no longer used (freed when it was the
- * library's own), and a captured graph is dropped (recapture).  Then repeat
+ * library's own; released for another context when it was the static array
+ * of md_init_static), and a captured graph is dropped (recapture).  Then repeat
  * the call that was refused.  Syncs. */
 int md_set_workspace(kamd_ctx *ctx, void *workspace, size_t ws_bytes);
 
@@ -376,12 +377,14 @@ int md_set_list_params(kamd_ctx *ctx, double skin, int32_t cell_div);
  * for windows = 1 in FP64.  Syncs. */
 int md_set_force_kernel(kamd_ctx *ctx, int32_t windows, int32_t wg_size);
 
-/* Statistics: host_out (host, FP64 [12]) = {steps, rebuilds, n_total,
+/* Statistics: host_out (host, FP64 [13]) = {steps, rebuilds, n_total,
  * list_rows, mean_list_len, max_list_len, skin, cell_div, mean_list_bytes,
  * windows (the force-kernel variant), fraction of list parts gathered from a
- * window, step-kernel threads per block}.  List lengths count partners at the last build (without
- * wavefront padding); mean_list_bytes is their stored size per particle (4
- * bytes per 32-bit entry, 2 per 16-bit entry).  Syncs. */
+ * window, step-kernel threads per block, mean_walked}.  List lengths count
+ * partners at the last build (without wavefront padding); mean_list_bytes is
+ * their stored size per particle (4 bytes per 32-bit entry, 2 per 16-bit
+ * entry); mean_walked is the number of entries the force kernels walk per
+ * particle, each list part padded to its wavefront's longest.  Syncs. */
 int md_stats(kamd_ctx *ctx, double *host_out);
 
 /* Checkpoint: the full dynamical state (positions, velocities, forces, image

@@ -25,6 +25,7 @@ constexpr int LIST_ROW_ALIGN = 4;        // neighbour rows are padded to this mu
 constexpr int CELL_SUBX = 4;             // list cells are sorted in sub-cells of a quarter
                                          // cell edge along x (cell_count/start/end per sub-cell)
 constexpr int VH_MAX_BINS = 1024;       // bins of the self van Hove histogram
+constexpr int SCAN_CHUNK = 2048;         // cells per block of the cell-range scan
 constexpr int LIST_UNROLL = 8;           // candidates per step of the list builder's scan
 // Force-kernel windows (mixed precisions): per wavefront and list part at
 // most STAGE_PIECES row pieces (9 stencil rows, each a main run and a wrapped
@@ -118,9 +119,8 @@ struct Dev {
     // cells and lists
     int32_t *cell_of, *rank, *cell_count, *cell_start, *cell_end, *order;
     int32_t *rb_force;    // per replica: rebuild at the next check regardless
-    int32_t *rb_any;      // [2]: number of waves, and of cells, that rebuild this step (gate kernel)
+    int32_t *rb_any;      // [2]: [0] the number of waves that rebuild this step (gate kernel)
     int32_t *rb_wlist;    // [nwaves]: those waves, replica by replica (gate kernel)
-    int32_t *rb_clist;    // [ncells]: those cells, replica by replica (gate kernel)
     uint32_t *maxdisp;    // per replica: max |r - r_build|^2 (float bits) since the last check
     int32_t *nbr;         // per wave: rows x 64 entries, see list_index
     int2 *kmax;           // per wave: entries of the A part, entries of the B part
@@ -161,6 +161,8 @@ struct Dev {
     int32_t dim;          // 3, or 2 for a planar system (z = vz = 0)
     int32_t ncells;
     int32_t rows;         // neighbour-list row capacity
+    int32_t scan_cps;     // scan chunks (SCAN_CHUNK cells) of the largest segment
+    int32_t *chunk_sum;   // [nseg][scan_cps]: particles of each scan chunk (segments of several chunks)
 };
 
 

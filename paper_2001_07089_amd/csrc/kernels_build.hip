@@ -11,23 +11,26 @@
 // rebuilt when some particle of the replica has moved more than skin/2 since
 // the last build (so no pair can enter the cutoff unseen).
 //
-// A rebuild runs as a gate and five kernels, all launched on every step, so
-// that the decision stays on the device and the step loop can be captured in
-// a HIP graph:
+// A rebuild runs as a gate and five (six) kernels, all launched on every
+// step, so that the decision stays on the device and the step loop can be
+// captured in a HIP graph:
 //   rb_gate       one block: rebuild flag of every replica (rebuild_flag),
-//                 worklists of the waves and of the cells of the replicas
-//                 that rebuild
-//   rb_assign     per listed wave: cell index and rank inside the cell of its
-//                 particles (one atomic per run of lanes that share a cell)
-//   rb_scan       per segment: exclusive scan of the counters -> cell ranges
+//                 worklist of the waves of the replicas that rebuild
+//   rb_assign     per listed wave: sub-cell index and rank inside the
+//                 sub-cell of its particles (one atomic per run of lanes that
+//                 share a sub-cell)
+//   rb_scan_sum   per chunk of a segment's cells (segments of several chunks
+//                 only): the particles of the chunk
+//   rb_scan       per chunk: exclusive scan of the counters -> cell ranges
 //   rb_scatter    per listed wave: provisional destination slot
-//   rb_sortgather per listed cell: order the cell by previous slot (a stable sort:
-//                 the result does not depend on atomic timing), gather the
-//                 particles' state into the scratch arrays, clear the counter
+//   rb_sortgather per listed particle: its rank by previous slot inside its
+//                 sub-cell (a stable sort: the result does not depend on
+//                 atomic timing), its state gathered into the scratch
+//                 arrays, the counter cleared
 //   rb_list       per listed wave: copy its state back, record the build
 //                 position, write its neighbour list
-// Every kernel returns at once when the worklists are empty; the
-// per-segment scan also skips replicas whose flag is clear.
+// Every kernel returns at once when the worklist is empty; the scan also
+// skips replicas whose flag is clear.
 #include <climits>
 
 #include "common_dev.hpp"
@@ -35,12 +38,11 @@
 namespace kamd {
 
 // The gate: one block evaluates the rebuild flag of every replica and writes
-// two worklists: the waves of the replicas that rebuild (rb_wlist) and their
-// cells (rb_clist), replica by replica in slot order, with the counts in
-// rb_any[0] and rb_any[1].  On the (most frequent) steps without a rebuild
-// every later kernel of the chain exits after one load; on a step where a
-// few replicas of a batch rebuild, the per-wave and per-cell kernels spread
-// just their work over the whole device.
+// the worklist of the waves of the replicas that rebuild (rb_wlist), replica
+// by replica in slot order, with their count in rb_any[0].  On the (most
+// frequent) steps without a rebuild every later kernel of the chain exits
+// after one load; on a step where a few replicas of a batch rebuild, the
+// per-wave kernels spread just their work over the whole device.
 constexpr int GATE_THREADS = 1024;
 
 // Append, for the replicas of one chunk (one per thread, n of them per
@@ -101,29 +103,20 @@ __device__ inline int gate_append(int32_t *out, int n, int first, GateShared &g)
 __global__ __launch_bounds__(GATE_THREADS) void k_rb_gate(Dev d)
 {
     __shared__ GateShared g;
-    int nwl = 0, ncl = 0;
+    int nwl = 0;
     for (int r0 = 0; r0 < d.nrep; r0 += GATE_THREADS) {
         const int r = r0 + threadIdx.x;
-        int nw = 0, w0 = 0, nc = 0, c0 = 0;
+        int nw = 0, w0 = 0;
         if (r < d.nrep) {
             const RepInfo &R = d.rep[r];
-            const SegInfo &SA = d.seg[R.seg[0]], &SB = d.seg[R.seg[1]];
             w0 = R.wave0;
-            c0 = SA.cell0;  // the replica's two segments have consecutive cells
-            if (rebuild_flag(d, r)) {
-                nw = R.wave1 - R.wave0;
-                nc = SA.ncell + SB.ncell;
-            }
+            if (rebuild_flag(d, r)) nw = R.wave1 - R.wave0;
         }
         // most steps rebuild nothing: skip the compaction (block-uniform)
         if (!__syncthreads_or(nw > 0)) continue;
         nwl += gate_append(d.rb_wlist + nwl, nw, w0, g);
-        ncl += gate_append(d.rb_clist + ncl, nc, c0, g);
     }
-    if (threadIdx.x == 0) {
-        d.rb_any[0] = nwl;
-        d.rb_any[1] = ncl;
-    }
+    if (threadIdx.x == 0) d.rb_any[0] = nwl;
 }
 
 // Worklist entry of this wavefront for the per-wave kernels that run one
@@ -180,69 +173,108 @@ __global__ __launch_bounds__(BLOCK) void k_rb_assign(Dev d)
         assign_wave(d, d.rb_wlist[i]);
 }
 
-// Exclusive scan of one segment's sub-cell counters into absolute slot
-// ranges [cell_start, cell_end).  One block of 1024 threads per segment; each
-// pass covers 8192 cells (8 consecutive per thread, wavefront shuffles, then
-// the 16 wavefront totals).  A cell's CELL_SUBX = 4 sub-cell counters are
-// read as one int4 and its ranges written as int4s, so a pass moves no more
-// loads and stores than a scan of the cells alone would.
+// Exclusive scan of each segment's sub-cell counters into absolute slot
+// ranges [cell_start, cell_end).  A segment's cells come in chunks of
+// SCAN_CHUNK (8 consecutive cells per thread of a SCAN_THREADS block; block
+// (segment, chunk) of a two-dimensional grid).  A segment of more than one
+// chunk first has each chunk's total written by k_rb_scan_sum; k_rb_scan then
+// starts each chunk at the segment's first slot plus the totals of the chunks
+// before it (at most d.scan_cps - 1 of them), so that the chunks of a large
+// system are scanned in parallel instead of one after another.  A cell's
+// CELL_SUBX = 4 sub-cell counters are read as one int4 and its ranges written
+// as int4s, so a pass moves no more loads and stores than a scan of the cells
+// alone would.
 static_assert(CELL_SUBX == 4, "the scan reads the sub-cells of a cell as one int4");
 
-__global__ __launch_bounds__(1024) void k_rb_scan(Dev d)
+__device__ inline int chunk_cells(const SegInfo &S, int c)
 {
-    __shared__ int wtot[16];
+    return min(S.ncell - c * SCAN_CHUNK, SCAN_CHUNK);
+}
+
+constexpr int SCAN_THREADS = SCAN_CHUNK / 8;
+constexpr int SCAN_WAVES = SCAN_THREADS / WAVE;
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_rb_scan_sum(Dev d)
+{
+    __shared__ int wtot[SCAN_WAVES];
+    if (d.rb_any[0] == 0) return;
+    const SegInfo &S = d.seg[blockIdx.x];
+    const int c = blockIdx.y;
+    const int n = chunk_cells(S, c);
+    if (n <= 0 || !rebuild_flag(d, S.rep)) return;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int4 *cnt = reinterpret_cast<const int4 *>(d.cell_count + CELL_SUBX * (S.cell0 + c * SCAN_CHUNK));
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int i = 8 * t + k;
+        if (i < n) {
+            const int4 v = cnt[i];
+            sum += v.x + v.y + v.z + v.w;
+        }
+    }
+    sum = wave_sum_i(sum);
+    if (lane == 0) wtot[wv] = sum;
+    __syncthreads();
+    if (t == 0) {
+        int tot = 0;
+        for (int k = 0; k < SCAN_WAVES; ++k) tot += wtot[k];
+        d.chunk_sum[blockIdx.x * d.scan_cps + c] = tot;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_rb_scan(Dev d)
+{
+    __shared__ int wtot[SCAN_WAVES];
     __shared__ int carry_s;
     if (d.rb_any[0] == 0) return;
     const SegInfo &S = d.seg[blockIdx.x];
-    if (!rebuild_flag(d, S.rep)) return;
+    const int c = blockIdx.y;
+    const int n = chunk_cells(S, c);
+    if (n <= 0 || !rebuild_flag(d, S.rep)) return;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (t == 0) {
-        carry_s = 0;
-        if (S.type == 0) atomicAdd(&d.counters[0], 1);
+        int carry = 0;  // the particles of the segment's chunks before this one
+        for (int k = 0; k < c; ++k) carry += d.chunk_sum[blockIdx.x * d.scan_cps + k];
+        carry_s = carry;
+        if (S.type == 0 && c == 0) atomicAdd(&d.counters[0], 1);
+    }
+    const int4 *cnt = reinterpret_cast<const int4 *>(d.cell_count + CELL_SUBX * (S.cell0 + c * SCAN_CHUNK));
+    int4 *cst = reinterpret_cast<int4 *>(d.cell_start + CELL_SUBX * (S.cell0 + c * SCAN_CHUNK));
+    int4 *cen = reinterpret_cast<int4 *>(d.cell_end + CELL_SUBX * (S.cell0 + c * SCAN_CHUNK));
+    int4 v[8];
+    int sum = 0;
+    const int i0 = 8 * t;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        v[k] = (i0 + k < n) ? cnt[i0 + k] : make_int4(0, 0, 0, 0);
+        sum += v[k].x + v[k].y + v[k].z + v[k].w;
+    }
+    int inc = sum;  // inclusive scan over the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    if (lane == 63) wtot[wv] = inc;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int k = 0; k < SCAN_WAVES; ++k) { const int x = wtot[k]; wtot[k] = run; run += x; }
     }
     __syncthreads();
-    const int n = S.ncell;
-    const int4 *cnt = reinterpret_cast<const int4 *>(d.cell_count + CELL_SUBX * S.cell0);
-    int4 *cst = reinterpret_cast<int4 *>(d.cell_start + CELL_SUBX * S.cell0);
-    int4 *cen = reinterpret_cast<int4 *>(d.cell_end + CELL_SUBX * S.cell0);
-    for (int base = 0; base < n; base += 8192) {
-        int4 v[8];
-        int sum = 0;
-        const int i0 = base + 8 * t;
+    int run = S.slot0 + carry_s + wtot[wv] + inc - sum;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            v[k] = (i0 + k < n) ? cnt[i0 + k] : make_int4(0, 0, 0, 0);
-            sum += v[k].x + v[k].y + v[k].z + v[k].w;
+    for (int k = 0; k < 8; ++k) {
+        if (i0 + k < n) {
+            int4 a, b;
+            a.x = run; run += v[k].x; b.x = run;
+            a.y = run; run += v[k].y; b.y = run;
+            a.z = run; run += v[k].z; b.z = run;
+            a.w = run; run += v[k].w; b.w = run;
+            cst[i0 + k] = a;
+            cen[i0 + k] = b;
         }
-        int inc = sum;  // inclusive scan over the wavefront
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int u = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += u;
-        }
-        if (lane == 63) wtot[wv] = inc;
-        __syncthreads();
-        if (t == 0) {
-            int run = 0;
-            for (int k = 0; k < 16; ++k) { const int x = wtot[k]; wtot[k] = run; run += x; }
-        }
-        __syncthreads();
-        int run = S.slot0 + carry_s + wtot[wv] + inc - sum;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            if (i0 + k < n) {
-                int4 a, b;
-                a.x = run; run += v[k].x; b.x = run;
-                a.y = run; run += v[k].y; b.y = run;
-                a.z = run; run += v[k].z; b.z = run;
-                a.w = run; run += v[k].w; b.w = run;
-                cst[i0 + k] = a;
-                cen[i0 + k] = b;
-            }
-        }
-        __syncthreads();
-        if (t == 1023) carry_s = run - S.slot0;
-        __syncthreads();
     }
 }
 
@@ -278,59 +310,31 @@ __device__ inline void gather_one(const Dev &d, int v, int t)
     d.smirror[t] = d.mirror[v];
 }
 
-// One wavefront per cell.  The members of the cell are grouped by sub-cell
-// (the scatter put them there); the destination of each member is its
-// sub-cell's start plus its rank by previous slot among the members of the
-// same sub-cell, which makes the counting sort stable.  Cells of up to 64
-// members rank in registers; larger ones (only tiny boxes with 1-2 cells per
-// edge) fall back to a loop over memory.
-__device__ inline void sortgather_cell(const Dev &d, int c)
-{
-    const int c0 = CELL_SUBX * c;
-    const int st = d.cell_start[c0];
-    const int m = d.cell_end[c0 + CELL_SUBX - 1] - st;
-    int bnd[CELL_SUBX];  // start of each sub-cell
-#pragma unroll
-    for (int k = 0; k < CELL_SUBX; ++k) bnd[k] = d.cell_start[c0 + k];
-    auto sub_of = [&](int p) __attribute__((always_inline)) {
-        int k = 0;
-#pragma unroll
-        for (int t = 1; t < CELL_SUBX; ++t) k += p >= bnd[t] ? 1 : 0;
-        return k;
-    };
-    const int lane = lane_id();
-    if (m <= WAVE) {
-        const int v = lane < m ? d.order[st + lane] : 0x7fffffff;
-        const int k = sub_of(st + lane);
-        int rank = 0;
-        for (int e2 = 0; e2 < m; ++e2)
-            rank += (__shfl(k, e2, 64) == k && __shfl(v, e2, 64) < v) ? 1 : 0;
-        int b = bnd[0];
-#pragma unroll
-        for (int t = 1; t < CELL_SUBX; ++t) b = k == t ? bnd[t] : b;
-        if (lane < m) gather_one(d, v, b + rank);
-    } else {
-        for (int e = lane; e < m; e += WAVE) {
-            const int v = d.order[st + e];
-            const int k = sub_of(st + e);
-            int rank = 0;
-            for (int e2 = 0; e2 < m; ++e2) rank += (sub_of(st + e2) == k && d.order[st + e2] < v) ? 1 : 0;
-            int b = bnd[0];
-#pragma unroll
-            for (int t = 1; t < CELL_SUBX; ++t) b = k == t ? bnd[t] : b;
-            gather_one(d, v, b + rank);
-        }
-    }
-    if (lane < CELL_SUBX) d.cell_count[c0 + lane] = 0;  // ready for the next rebuild
-}
-
+// One thread per particle of the replicas that rebuild.  The scatter put the
+// members of each sub-cell together in `order`, in the order of the atomics
+// that counted them; a particle's destination is its sub-cell's start plus
+// its rank by previous slot among those members (a loop over the sub-cell, a
+// few particles), which makes the counting sort stable.  Each member also
+// clears its sub-cell's counter for the next rebuild (a sub-cell without
+// members was never counted).
 __global__ __launch_bounds__(BLOCK) void k_rb_sortgather(Dev d)
 {
-    const int ncl = d.rb_any[1];  // cells of the replicas that rebuild
-    if (d.rb_any[0] == 0) return;
+    const int nact = d.rb_any[0];
+    if (nact == 0) return;
     const int stride = gridDim.x * WAVES_PER_BLOCK;
-    for (int i = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); i < ncl; i += stride)
-        sortgather_cell(d, d.rb_clist[i]);
+    for (int i = blockIdx.x * WAVES_PER_BLOCK + (threadIdx.x >> 6); i < nact; i += stride) {
+        const int w = d.rb_wlist[i];
+        const SegInfo &S = d.seg[d.wave_seg[w]];
+        const int s = w * WAVE + lane_id();
+        if (s - S.slot0 < S.n) {
+            const int sc = d.cell_of[s];
+            const int st = d.cell_start[sc], en = d.cell_end[sc];
+            int rank = 0;
+            for (int e = st; e < en; ++e) rank += d.order[e] < s ? 1 : 0;
+            gather_one(d, s, st + rank);
+            d.cell_count[sc] = 0;
+        }
+    }
 }
 
 // Neighbour lists.  One thread per particle.  Entries [0, kA) of a list hold
@@ -892,7 +896,6 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
 
 static inline int nblk_slots(const Dev &d) { return (d.nwaves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK; }
 constexpr int CHAIN_MAX_BLOCKS = 1024;  // grid cap of the grid-stride chain kernels
-constexpr int SORT_MAX_BLOCKS = 1 << 16;  // grid cap of the per-cell sort-gather
 static inline int nblk_capped(int waves) { return std::min((waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, CHAIN_MAX_BLOCKS); }
 
 hipError_t launch_rb_gate(const Dev &d, hipStream_t s)
@@ -907,7 +910,9 @@ hipError_t launch_rb_assign(const Dev &d, hipStream_t s)
 }
 hipError_t launch_rb_scan(const Dev &d, int nseg, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rb_scan, dim3(nseg), dim3(1024), 0, s, d);
+    const dim3 grid(nseg, d.scan_cps);
+    if (d.scan_cps > 1) hipLaunchKernelGGL(k_rb_scan_sum, grid, dim3(SCAN_THREADS), 0, s, d);
+    hipLaunchKernelGGL(k_rb_scan, grid, dim3(SCAN_THREADS), 0, s, d);
     return hipGetLastError();
 }
 hipError_t launch_rb_scatter(const Dev &d, hipStream_t s)
@@ -917,10 +922,7 @@ hipError_t launch_rb_scatter(const Dev &d, hipStream_t s)
 }
 hipError_t launch_rb_sortgather(const Dev &d, hipStream_t s)
 {
-    // one wavefront per cell, over a grid capped well inside the 2^32
-    // work-item limit of a launch dimension (larger grids walk with a stride)
-    const int nb = std::min((d.ncells + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK, SORT_MAX_BLOCKS);
-    hipLaunchKernelGGL(k_rb_sortgather, dim3(nb), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_rb_sortgather, dim3(nblk_capped(d.nwaves)), dim3(BLOCK), 0, s, d);
     return hipGetLastError();
 }
 hipError_t launch_rb_list(const Dev &d, int cell_div, hipStream_t s)

@@ -27,6 +27,7 @@ struct Plan {
     std::vector<RepInfo> rinfo;
     std::vector<int32_t> wave_seg;
     int32_t npad = 0, nwaves = 0, ncells = 0, rows = 0, n_total = 0;
+    int32_t scan_cps = 1;     // scan chunks of the largest segment
     int64_t ncells_wide = 0;  // the same count without 32-bit truncation
     bool fp64 = false;        // FP64 precision: two packed position buffers
 };
@@ -275,6 +276,7 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
             for (int w = 0; w < S.npad / WAVE; ++w) P.wave_seg.push_back(R.seg[t]);
             slot += S.npad;
             cell += fits ? S.ncell : 0;
+            P.scan_cps = std::max(P.scan_cps, (S.ncell + SCAN_CHUNK - 1) / SCAN_CHUNK);
             P.segs.push_back(S);
         }
         R.wave1 = slot / WAVE;
@@ -419,14 +421,14 @@ static void carve_fixed(Dev &d, CtxBufs &b, const Shape &z, Carve &k)
 }
 
 // The part that depends on the list parameters: per sub-cell counters and
-// ranges, the rebuild cell worklist and the neighbour list.
+// ranges, the scan chunk totals and the neighbour list.
 static void carve_list(Dev &d, const Plan &P, Carve &k)
 {
     const size_t nsub = (size_t)CELL_SUBX * P.ncells;
     d.cell_count = k.take<int32_t>(nsub);
     d.cell_start = k.take<int32_t>(nsub);
     d.cell_end = k.take<int32_t>(nsub);
-    d.rb_clist = k.take<int32_t>(P.ncells);
+    d.chunk_sum = k.take<int32_t>(P.segs.size() * (size_t)P.scan_cps);
     d.nbr = k.take<int32_t>((size_t)P.rows * P.npad);
 }
 
@@ -531,6 +533,7 @@ static void bind_workspace(kamd_ctx *c, const Plan &P)
     d.dim = dim_of(&c->cfg);
     d.rows = P.rows;
     d.ncells = P.ncells;
+    d.scan_cps = P.scan_cps;
     d.rdf_cells_cap = (int64_t)c->shape.rdf_cells;
     d.stage_ok = c->cfg.precision != KAMD_PREC_FP64 && c->stage_windows;
     d.ring_cap = ring_rows(&c->cfg);
@@ -1439,6 +1442,10 @@ extern "C" int md_set_workspace(kamd_ctx *c, void *workspace, size_t ws_bytes)
     HIPCHK(c, hipMemcpyAsync(workspace, c->ws, cur, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (c->ws_owned) (void)hipFree(c->ws);
+    if (c->static_device >= 0) {  // the device's static array is free for another context
+        release_static_workspace(c->static_device);
+        c->static_device = -1;
+    }
     c->ws = (char *)workspace;
     c->ws_bytes = ws_bytes;
     c->ws_owned = false;
@@ -1456,13 +1463,22 @@ extern "C" int md_stats(kamd_ctx *c, double *host_out)
     int32_t cnt[8];
     HIPCHK(c, hipMemcpyAsync(cnt, c->d.counters, 32, hipMemcpyDeviceToHost, c->stream));
     std::vector<int32_t> nlen(c->d.npad_total), id(c->d.npad_total);
-    std::vector<int2> lb(c->d.nwaves);
+    std::vector<int2> lb(c->d.nwaves), km(c->d.nwaves);
     HIPCHK(c, hipMemcpyAsync(nlen.data(), c->d.nlen, 4 * nlen.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(id.data(), c->d.id, 4 * id.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(lb.data(), c->d.lbase, sizeof(int2) * lb.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(km.data(), c->d.kmax, sizeof(int2) * km.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     int64_t parts_staged = 0;
     for (const int2 &b : lb) parts_staged += (b.x <= -2) + (b.y <= -2);
+    // entries every lane of a wavefront walks (its parts padded to the
+    // wavefront's longest), summed over the real particles
+    double walked = 0.0;
+    for (size_t w = 0; w < km.size(); ++w) {
+        int real = 0;
+        for (int l = 0; l < WAVE; ++l) real += id[w * WAVE + l] >= 0;
+        walked += (double)real * (km[w].x + km[w].y);
+    }
     double sum = 0.0, mx = 0.0, bytes = 0.0;
     int64_t cntr = 0;
     for (size_t i = 0; i < nlen.size(); ++i)
@@ -1485,6 +1501,7 @@ extern "C" int md_stats(kamd_ctx *c, double *host_out)
     host_out[9] = c->d.stage_ok ? 1.0 : 0.0;
     host_out[10] = lb.empty() ? 0.0 : (double)parts_staged / (2.0 * lb.size());
     host_out[11] = (double)(WAVE * c->force_wpb);
+    host_out[12] = cntr ? walked / cntr : 0.0;
     return KAMD_OK;
 }
 

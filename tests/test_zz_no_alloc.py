@@ -97,3 +97,31 @@ def test_static_context_refuses_a_system_beyond_the_array():
         md.md_init_static(cfg, reps, md.State(), 0)
     assert e.value.code == md.KAMD_ENOMEM
     assert b"static array" in md.lib().md_last_error(None)
+
+
+def test_a_static_context_moved_to_a_caller_workspace_frees_the_array():
+    """md_set_workspace moves a static context into the caller's block; the
+    static array is then free for the next md_init_static, and the moved
+    context still steps as md_init's does."""
+    reps, pos, vel = inputs([1500], 77)
+    ref = md.System(reps, precision="mixed_fixed", positions=pos, velocities=vel)
+    ctx, stream, t, img = static_context(ref, pos, vel)
+    torch = ref.torch
+    need = md.md_workspace_needed(ctx)
+    with torch.cuda.stream(stream):
+        ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    stream.synchronize()
+    md.md_set_workspace(ctx, ws.data_ptr(), need)
+    ctx2, stream2, t2, img2 = static_context(ref, pos, vel)  # the array is free again
+    md.md_step_nve(ctx, 40)
+    md.md_step_nve(ctx2, 40)
+    ref.step_nve(40)
+    b = ref.numpy()
+    for c, s_, tt, ii in ((ctx, stream, t, img), (ctx2, stream2, t2, img2)):
+        a, _ = host(s_, tt, ii)
+        for k in KEYS:
+            assert np.array_equal(a[k], b[k]), k
+        assert md.md_status(c) == 0
+    md.md_destroy(ctx2)
+    md.md_destroy(ctx)
+    ref.close()
