@@ -236,6 +236,7 @@ def roofline(prof, stats, n, precision):
     pairs = prof["pairs"]
     useful = pairs * FLOP_PER_PAIR / sec / 1e12
     candidates = stats["mean_list_len"] * n
+    walked = stats.get("mean_walked", stats["mean_list_len"]) * n  # padded to each wavefront's longest
     kname = kernel_name(precision, int(stats["windows"]), int(stats["wg_size"]))
     traffic = stored_traffic(stats["skin"], int(stats["cell_div"]), precision, n, kname)
     alg_bytes = n * INTEGRATION_BYTES
@@ -243,7 +244,8 @@ def roofline(prof, stats, n, precision):
             "traffic": traffic, "kernel": kname, "kernel_ms": prof["force_ms"],
             "work_unit": "ordered in-cutoff pair", "flop_per_unit": FLOP_PER_PAIR, "units_per_launch": pairs,
             "frac_of_nonpacked_peak": useful / FP32_PEAK_NONPACKED,
-            "issued_tflops": candidates * FLOP_PER_PAIR / sec / 1e12, "list_candidates_per_launch": candidates,
+            "issued_tflops": walked * FLOP_PER_PAIR / sec / 1e12, "list_candidates_per_launch": candidates,
+            "walked_entries_per_launch": walked,
             "hbm_view": {"algorithmic_bytes_per_launch": alg_bytes, "bytes_per_atom_step": INTEGRATION_BYTES,
                          "achieved_gbs": alg_bytes / sec / 1e9, "peak_gbs": HBM_PEAK,
                          "frac": alg_bytes / sec / 1e9 / HBM_PEAK,

@@ -22,16 +22,19 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_roofline_prices_useful_pair_flops_against_the_fp32_peak():
     """achieved = ordered in-cutoff pairs x 19 FLOP / mean launch time, over
-    157.3 TFLOP/s; issued work counts the list candidates; the HBM view
+    157.3 TFLOP/s; issued work counts the entries the kernel walks (padding
+    included); the HBM view
     counts 150 bytes per atom-step."""
     prof = {"force_ms": 0.25, "pairs": 67216584.0}
-    stats = {"mean_list_len": 104.0, "skin": 0.4, "cell_div": 1.0, "windows": 1.0, "wg_size": 128.0}
+    stats = {"mean_list_len": 104.0, "skin": 0.4, "cell_div": 1.0, "windows": 1.0, "wg_size": 128.0,
+             "mean_walked": 126.0}
     n = 1 << 20
     r = bench.roofline(prof, stats, n, "mixed_fixed")
     assert r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
     assert r["achieved"] == pytest.approx(67216584.0 * 19 / 0.25e-3 / 1e12)
     assert r["frac"] == pytest.approx(r["achieved"] / 157.3)
-    assert r["issued_tflops"] == pytest.approx(104.0 * n * 19 / 0.25e-3 / 1e12)
+    assert r["issued_tflops"] == pytest.approx(126.0 * n * 19 / 0.25e-3 / 1e12)
+    assert r["list_candidates_per_launch"] == 104.0 * n
     assert r["hbm_view"]["achieved_gbs"] == pytest.approx(n * 150 / 0.25e-3 / 1e9)
     assert r["kernel"] == "k_force_mixed<true,false,true,true,2>"
     assert bench.kernel_name("fp64") == "k_force_fp64<false,true,4>"

@@ -744,6 +744,9 @@ def test_list_statistics_count_16bit_entries():
     log(f"  bytes per partner {ratio:.3f}")
     assert 2.3 < ratio < 3.0
     assert st["max_list_len"] <= st["list_rows"]
+    # every lane walks its partners, its own slot and the padding up to the
+    # wavefront's longest part
+    assert st["mean_list_len"] + 1 <= st["mean_walked"] <= 2 * st["list_rows"]
     assert st["windows"] == 0 and st["staged_fraction"] == 0
     # window entries are 16-bit offsets: 2 bytes per partner in a part whose
     # window fits, so staging can only lower the bytes per partner
