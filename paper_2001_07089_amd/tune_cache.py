@@ -67,11 +67,15 @@ def store(path: str, key: str, entry: dict) -> None:
 
 
 def device_name(torch_module=None) -> str:
+    """The GPU as the picks depend on it: its architecture (with target
+    features) and compute-unit count.  The marketing name is left out: the
+    runtime reports it differently in different environments (a generic name,
+    or none under some profilers)."""
     import torch
     t = torch_module or torch
     p = t.cuda.get_device_properties(t.cuda.current_device())
-    arch = getattr(p, "gcnArchName", "")
-    return f"{p.name}:{arch}" if arch else p.name
+    arch = getattr(p, "gcnArchName", "") or p.name
+    return f"{arch}:{p.multi_processor_count}CU"
 
 
 def tune(system, probe_steps: int = 100, path: str = None, device: str = None, refresh: bool = False) -> dict:

@@ -2,6 +2,7 @@
 storage.  The two library calls are replaced by recording fakes, so this runs
 without a GPU."""
 import json
+import os
 import types
 
 import pytest
@@ -83,3 +84,23 @@ def test_corrupt_cache_is_a_miss(tmp_path, fakes):
     out = tune_cache.tune(s, 10, path=str(path), device="d")
     assert not out["cached"] and fakes["tune"] == 1
     assert out["key"] in json.load(open(path))
+
+
+def test_device_name_is_arch_and_compute_units():
+    """The key leaves out the marketing name, which the runtime reports
+    differently in different environments (empty under some profilers)."""
+    props = types.SimpleNamespace(name="", gcnArchName="gfx950:sramecc+:xnack-", multi_processor_count=256)
+    fake = types.SimpleNamespace(cuda=types.SimpleNamespace(current_device=lambda: 0,
+                                                            get_device_properties=lambda i: props))
+    assert tune_cache.device_name(fake) == "gfx950:sramecc+:xnack-:256CU"
+    props.name = "AMD Radeon Graphics"
+    assert tune_cache.device_name(fake) == "gfx950:sramecc+:xnack-:256CU"
+
+
+def test_shipped_picks_are_well_formed():
+    data = tune_cache.load(os.path.join(os.path.dirname(md.__file__), "tuned", "autotune.json"))
+    assert data
+    for key, e in data.items():
+        assert key.count("|") == 5
+        assert 0.2 <= e["skin"] <= 0.5 and e["cell_div"] in (1, 2)
+        assert e["windows"] in (0, 1) and e["wg_size"] in (64, 128, 256)
