@@ -1,0 +1,108 @@
+"""The rebuild chain on replicas large enough that each type segment's cells
+span several scan chunks (2048 cells each), with replicas that rebuild on
+different steps (different temperatures), so that the chunked scan and the
+per-particle sort-gather run with some replicas rebuilding and others not.
+MIXED_FIXED forces do not depend on the order of the sums, and the replicas
+of a batch do not interact, so each replica's trajectory in the batch must
+equal, bit for bit, its trajectory run alone; the forces at the end are also
+checked against the FP64 oracle (Eq. (KAFix))."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2001_07089_amd import md
+from paper_2001_07089_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("x", "y", "z", "vx", "vy", "vz", "ax", "ay", "az")
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# (n, rho, T, seed): at skin 0.3 each type segment has 13^3 = 2197 cells
+# (two scan chunks, the second of 149 cells) in the first two replicas and
+# 17^3 = 4913 (three chunks) in the third
+REPS = [(60000, 1.2, 0.45, 51), (70000, 1.25, 2.0, 52), (150000, 1.2, 1.0, 53)]
+
+
+def _reps(sel):
+    out = []
+    for n, rho, T, seed in sel:
+        out.append((n, W.n_a_for(n), W.box_for(n, rho), T, seed))
+    return out
+
+
+def _start(sel):
+    pos, vel = [[], [], []], [[], [], []]
+    for n, rho, T, seed in sel:
+        L = W.box_for(n, rho)
+        for k, a in enumerate(W.lattice_config(n, L, seed, 0.1)):
+            pos[k].append(a)
+        for k, a in enumerate(W.gaussian_velocities(n, math.sqrt(T), seed + 7)):
+            vel[k].append(a)
+    return [np.concatenate(p) for p in pos], [np.concatenate(v) for v in vel]
+
+
+def _run(sel, steps):
+    pos, vel = _start(sel)
+    s = md.System(_reps(sel), precision="mixed_fixed", positions=pos, velocities=vel, skin=0.3, auto_sync=False)
+    s.step_nve(steps)
+    s.sync()
+    out = s.numpy(KEYS)
+    img = s.images()
+    st = md.md_stats(s.ctx)
+    assert s.status() == 0
+    s.close()
+    return out, img, st
+
+
+def test_batch_with_multi_chunk_segments_equals_replicas_alone():
+    steps = 300
+    log(f"case rebuild chain, batch {[r[0] for r in REPS]}, {steps} steps")
+    ref, ref_img, st = _run(REPS, steps)
+    log(f"  batch rebuilds {st['rebuilds']:.0f} (summed over replicas)")
+    off, counts = 0, []
+    for r in REPS:
+        alone, img, st1 = _run([r], steps)
+        counts.append(st1["rebuilds"])
+        log(f"  n={r[0]} T={r[2]}: rebuilds alone {st1['rebuilds']:.0f}")
+        sl = slice(off, off + r[0])
+        for k in KEYS:
+            assert np.array_equal(ref[k][sl], alone[k]), (r, k)
+        assert np.array_equal(ref_img[:, sl], img), r
+        off += r[0]
+    # every replica rebuilt as often in the batch as alone, and not all as
+    # often as each other: some steps rebuilt some replicas and not others
+    assert st["rebuilds"] == sum(counts)
+    assert len(set(counts)) > 1
+
+
+def test_forces_after_partial_rebuilds_match_oracle():
+    sel = REPS[:2]
+    s_pos, s_vel = _start(sel)
+    s = md.System(_reps(sel), precision="mixed_fixed", positions=s_pos, velocities=s_vel, skin=0.3,
+                  auto_sync=False)
+    s.step_nve(200)
+    s.forces()
+    s.sync()
+    a = s.numpy(("x", "y", "z", "ax", "ay", "az"))
+    assert s.status() == 0
+    off = 0
+    for n, rho, T, seed in sel:
+        sl = slice(off, off + n)
+        L = W.box_for(n, rho)
+        fx, fy, fz, _, _ = O.forces(a["x"][sl], a["y"][sl], a["z"][sl], W.n_a_for(n), L, "cell")
+        num = sum(np.sum((a[k][sl] - f) ** 2) for k, f in zip(("ax", "ay", "az"), (fx, fy, fz)))
+        den = np.sum(fx ** 2 + fy ** 2 + fz ** 2)
+        err = math.sqrt(num / den)
+        log(f"  n={n}: normwise {err:.3e}")
+        assert err <= 1e-5
+        off += n
+    s.close()
