@@ -104,16 +104,31 @@ __global__ __launch_bounds__(BLOCK) void k_kick_drift(Dev d, double dt, int want
 }
 
 // Per-replica sum of the 4 per-wave partials (fixed order).  what: 0 -> rsum.
+// Each thread reads a wave's four partials as one 32-byte load, four waves
+// (BLOCK apart) per pass, so that a replica of many waves (16,384 at N =
+// 2^20) is read in a quarter of the dependent passes.
 __global__ __launch_bounds__(BLOCK) void k_rep_reduce(Dev d, int mask)
 {
     __shared__ double red[4][BLOCK];
     const int r = blockIdx.x;
     const RepInfo &R = d.rep[r];
+    const double4 *wr = reinterpret_cast<const double4 *>(d.wred);
+    auto pick = [mask](const double4 &v, int k) __attribute__((always_inline)) {
+        const double x = k == 0 ? v.x : (k == 1 ? v.y : (k == 2 ? v.z : v.w));
+        return (mask & (1 << k)) ? x : 0.0;
+    };
     double a[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int w = R.wave0 + threadIdx.x; w < R.wave1; w += BLOCK)
+    int w = R.wave0 + threadIdx.x;
+    for (; w + 3 * BLOCK < R.wave1; w += 4 * BLOCK) {
+        const double4 v0 = wr[w], v1 = wr[w + BLOCK], v2 = wr[w + 2 * BLOCK], v3 = wr[w + 3 * BLOCK];
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (mask & (1 << k)) a[k] += d.wred[4 * w + k];
+        for (int k = 0; k < 4; ++k) a[k] += (pick(v0, k) + pick(v1, k)) + (pick(v2, k) + pick(v3, k));
+    }
+    for (; w < R.wave1; w += BLOCK) {
+        const double4 v = wr[w];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] += pick(v, k);
+    }
 #pragma unroll
     for (int k = 0; k < 4; ++k) red[k][threadIdx.x] = a[k];
     __syncthreads();
