@@ -1,10 +1,12 @@
 """GPU parity at the full workload sizes, in the launch configuration bench.py
-times (single 2^20-particle system; 256-replica batch), on inputs from the
+times (single 2^20-particle system with the shipped tuned pick; 256-replica
+batch; the whole 64-replica workload with sampled replicas), on inputs from the
 seeded workload generator.  The oracle evaluates every force with its
 cell-list routine (OpenMP); the RDF at N = 32000 is compared bin by bin
 against the O(N^2) oracle; the MSD at 2^20 against a closed form.
 """
 import math
+import os
 import sys
 
 import numpy as np
@@ -237,4 +239,82 @@ def test_batch_large_three_densities_match_oracle():
         assert err <= 1e-5
         assert obs[i, 0] == pytest.approx(pe, rel=1e-5)
     assert s.status() == 0
+    s.close()
+
+
+def test_headline_configuration_matches_oracle(tmp_path):
+    """The single-system benchmark as bench.py runs it: N = 2^20 from the
+    lattice start, the list and step-kernel pick shipped for this GPU applied
+    through the tuning cache (a copy, so that a miss on another GPU tunes
+    without touching the shipped file), stochastic bath, then NVE steps
+    replayed from a graph.  Forces at the final positions against the
+    oracle's cell-list routine; the fixed-point force sum is exactly zero."""
+    import shutil
+    from paper_2001_07089_amd import tune_cache
+    wl = W.ka_large()
+    r = wl.replicas[0]
+    log(f"case headline configuration n={r.n}")
+    s = md.System([(r.n, r.n_a, r.box, r.temperature, r.seed)], precision="mixed_fixed", dt=wl.dt,
+                  init="lattice", skin=0.3, auto_sync=False)
+    s.step_nvt(300, md.NVT_STOCHASTIC, n_reassign=10)
+    cache = tmp_path / "autotune.json"
+    shutil.copy(os.path.join(os.path.dirname(md.__file__), "tuned", "autotune.json"), cache)
+    pick = tune_cache.tune(s, 60, path=str(cache))
+    log(f"  pick {pick}")
+    st = md.md_stats(s.ctx)
+    assert (st["skin"], st["cell_div"], st["windows"], st["wg_size"]) == \
+        (pick["skin"], pick["cell_div"], pick["windows"], pick["wg_size"])
+    s.step_nvt(200, md.NVT_STOCHASTIC, n_reassign=50)
+    s.capture(200)
+    s.launch()
+    s.sync()
+    assert s.status() == 0
+    a = s.numpy()
+    for k in ("ax", "ay", "az"):
+        q = np.rint(a[k] * 2.0 ** 26).astype(np.int64)
+        assert int(q.sum()) == 0
+    fx, fy, fz, _, _ = O.forces(a["x"], a["y"], a["z"], r.n_a, r.box, "cell")
+    err = normwise((a["ax"], a["ay"], a["az"]), (fx, fy, fz))
+    log(f"  normwise {err:.3e}, rebuilds {md.md_stats(s.ctx)['rebuilds']:.0f}")
+    assert err <= 1e-5
+    s.close()
+
+
+def test_batch_large_full_workload_sampled_replicas_match_oracle():
+    """The whole 64-replica workload (N 5e4-5e5, densities 1.1 / 1.2 / 1.3,
+    sum N = 1.8e7) as bench.py runs it: admitted by the planner, lattice
+    start, mixed precision, stochastic bath, then NVE steps replayed from a
+    graph.  At the final positions, the forces and potential energy of four
+    sampled replicas (the smallest and the largest, and the largest of each
+    other density) against the oracle's cell-list routine."""
+    wl = W.ka_batch_large()
+    reps = [(r.n, r.n_a, r.box, r.temperature, r.seed) for r in wl.replicas]
+    cfg = md.make_config("mixed", wl.dt, 0.3, md.INIT_LATTICE)
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    adm, cnt = md.md_admit(cfg, md.make_replicas(reps), int(free * 0.8))
+    assert cnt == len(reps)
+    log(f"case batch-large full workload: {len(reps)} replicas, {wl.n_total} particles")
+    s = md.System(reps, precision="mixed", dt=wl.dt, skin=0.3, init="lattice", auto_sync=False)
+    s.step_nvt(100, md.NVT_STOCHASTIC, n_reassign=10)
+    s.capture(100)
+    s.launch()
+    obs = s.forces(energy=True)
+    s.sync()
+    assert s.status() == 0
+    order = sorted(range(len(wl.replicas)), key=lambda i: wl.replicas[i].n)
+    pick = {order[0], order[-1]}
+    for rho in (1.1, 1.2, 1.3):
+        cands = [i for i in order if abs(wl.replicas[i].rho - rho) < 1e-9]
+        if cands:
+            pick.add(cands[-1])
+    a = s.numpy(("x", "y", "z", "ax", "ay", "az"))
+    for i in sorted(pick):
+        r = wl.replicas[i]
+        sl = s.replica_slice(i)
+        fx, fy, fz, pe, _ = O.forces(a["x"][sl], a["y"][sl], a["z"][sl], r.n_a, r.box, "cell")
+        err = normwise((a["ax"][sl], a["ay"][sl], a["az"][sl]), (fx, fy, fz))
+        log(f"  replica {i}: n={r.n} rho={r.rho} normwise {err:.3e}")
+        assert err <= 1e-5
+        assert obs[i, 0] == pytest.approx(pe, rel=1e-5)
     s.close()
