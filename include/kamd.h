@@ -84,8 +84,15 @@ enum {
     KAMD_DEV_FORCE_RANGE = 4u,   /* MIXED_FIXED: a pair came so close that its force
                                     reached 2^25 (beyond it the 2^-26-unit rounding is
                                     no longer exact), or a net force exceeded 1e8     */
-    KAMD_DEV_LIST_FORMAT = 8u    /* internal: a force kernel met a list part stored in
+    KAMD_DEV_LIST_FORMAT = 8u,   /* internal: a force kernel met a list part stored in
                                     a format it does not read, and skipped it          */
+    KAMD_DEV_RUNAWAY = 16u       /* a particle moved more than half the smallest sigma
+                                    in one step (a normal step moves about a hundredth
+                                    of that): forces too large for the time step, as
+                                    the close pairs of a random start give (the runaway
+                                    positions and velocities of Sec. II.F).  The lists
+                                    stay valid (they are checked every step); the
+                                    trajectory is not to be trusted                    */
 };
 
 /* Pair model: epsilon and sigma per pair type in the order AA, AB, BB, and the

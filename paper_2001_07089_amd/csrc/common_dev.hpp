@@ -99,10 +99,13 @@ __device__ inline void drift_core(const Dev &d, int s, const RepInfo &R, double 
     int32_t im[3] = {d.img[s], d.img[np + s], d.img[2 * np + s]};
     uint32_t q[3];
     bool fin = true;
+    double step2 = 0.0;  // squared length of this step's move (runaway check)
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const double g = a[k] - xi * v[k];
-        r[k] = fma(dt, fma(0.5 * dt, g, v[k]), r[k]);
+        const double u = fma(0.5 * dt, g, v[k]);
+        step2 = fma(u, u, step2);
+        r[k] = fma(dt, u, r[k]);
         vn[k] = fma(c, a[k] - (xi + xia) * v[k], v[k]);
         fin = fin && isfinite(r[k]) && isfinite(vn[k]);
         r[k] = wrap_img(r[k], L, invL, im[k]);
@@ -118,6 +121,7 @@ __device__ inline void drift_core(const Dev &d, int s, const RepInfo &R, double 
     const float h = (float)(R.L * 2.3283064365386963e-10);
     d2 = (ex * ex + ey * ey + ez * ez) * (h * h);
     if (!fin) set_err(d.err, KAMD_DEV_NONFINITE);
+    if (step2 * (dt * dt) > R.run2) set_err(d.err, KAMD_DEV_RUNAWAY);
 }
 
 __device__ inline void drift_one(const Dev &d, int s, int rep, double dt, double xi, double xia,

@@ -72,6 +72,7 @@ struct RepInfo {
     int32_t nc;            // list cells per box edge
     double skin;
     double disp_thr2;      // rebuild when max |dr|^2 exceeds this (real units)
+    double run2;           // a single step's |dr|^2 beyond this is a runaway (real units)
     // pair constants in the u32 fixed-point length unit h = L / 2^32
     float rc2_fx[3];       // r_c(ab)^2 / h^2
     float rl2_fx[3];       // (r_c(ab) + skin)^2 / h^2, slightly enlarged

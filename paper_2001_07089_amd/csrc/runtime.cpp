@@ -243,6 +243,10 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
         R.skin = skin;
         const double half = 0.5 * skin;
         R.disp_thr2 = half * half * (1.0 - 1e-5);
+        // a move of half the smallest sigma in one step (a normal step moves
+        // about a hundredth of that) marks an unstable, runaway integration
+        const double smin = std::min(cfg->model.sigma[0], std::min(cfg->model.sigma[1], cfg->model.sigma[2]));
+        R.run2 = 0.25 * smin * smin;
         const int nc = cells_per_edge(K.box);
         R.nc = nc;
         const double h = K.box / 4294967296.0;

@@ -22,7 +22,7 @@ PREC_FP64, PREC_MIXED, PREC_MIXED_FIXED = 0, 1, 2
 F_FORCE, F_ENERGY, F_VIRIAL = 1, 2, 4
 NVT_STOCHASTIC, NVT_NOSE_HOOVER = 0, 1
 INIT_GIVEN, INIT_RSA, INIT_LATTICE = 0, 1, 2
-DEV_NONFINITE, DEV_LIST_OVERFLOW, DEV_FORCE_RANGE, DEV_LIST_FORMAT = 1, 2, 4, 8
+DEV_NONFINITE, DEV_LIST_OVERFLOW, DEV_FORCE_RANGE, DEV_LIST_FORMAT, DEV_RUNAWAY = 1, 2, 4, 8, 16
 PRECISIONS = {"fp64": PREC_FP64, "mixed": PREC_MIXED, "mixed_fixed": PREC_MIXED_FIXED}
 
 # Kob-Andersen parameters (Sec. II.B), pair order AA, AB, BB.

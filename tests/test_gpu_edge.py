@@ -150,3 +150,23 @@ def test_batch_mixing_degenerate_and_ordinary_replicas(prec):
     a = s.numpy()
     assert a["x"][0] == pytest.approx(1.5 + 40 * s.cfg.dt * 0.3, rel=1e-12)
     s.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed_fixed"])
+def test_runaway_pair_sets_its_bit(prec):
+    """Two A particles 0.5 apart, as a random start can leave them (Sec. II.F):
+    the repulsion throws them apart by several sigma in the first step, far
+    more than half the smallest sigma, which sets KAMD_DEV_RUNAWAY and
+    nothing else; a pair at r = 1.1 moves a tiny fraction of it and sets
+    nothing."""
+    L = 6.0
+    v0 = (np.zeros(2), np.zeros(2), np.zeros(2))
+    for r, expect in ((0.5, True), (1.1, False)):
+        log(f"case runaway {prec} r={r}")
+        p = (np.array([2.0, 2.0 + r]), np.array([3.0, 3.0]), np.array([3.0, 3.0]))
+        s = build([(p, v0, 2, L, 1.0)], prec)
+        assert s.status() == 0
+        s.step_nve(1)
+        w = s.status()
+        assert w == (md.DEV_RUNAWAY if expect else 0), (r, w)
+        s.close()
