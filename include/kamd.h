@@ -412,6 +412,11 @@ int md_profile(kamd_ctx *ctx, int32_t nsteps, double *host_out);
  * bits) in *word; returns KAMD_EDEVICE when it is non-zero.  Syncs. */
 int md_status(kamd_ctx *ctx, uint32_t *word);
 
+/* Clear the sticky device error word (after md_status reported it and the
+ * caller dealt with the cause, e.g. relaxed a runaway start with a smaller
+ * time step, Sec. II.F).  Syncs. */
+int md_clear_status(kamd_ctx *ctx);
+
 /* Message of the last error on this context (or of the last failed md_init
  * when ctx is NULL).  Never NULL. */
 const char *md_last_error(const kamd_ctx *ctx);

@@ -1849,6 +1849,15 @@ extern "C" int md_status(kamd_ctx *c, uint32_t *word)
     return KAMD_OK;
 }
 
+extern "C" int md_clear_status(kamd_ctx *c)
+{
+    if (!c) return fail(nullptr, KAMD_EINVAL, "null context");
+    const uint32_t zero = 0;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->d.err, &zero, 4, hipMemcpyHostToDevice));
+    return KAMD_OK;
+}
+
 extern "C" int md_destroy(kamd_ctx *c)
 {
     if (!c) return KAMD_OK;

@@ -36,7 +36,7 @@ EXPORTED = ("md_workspace_size", "md_admit", "md_init", "md_build_cells", "md_fo
             "md_stats", "md_get_state", "md_set_state", "md_profile", "md_status", "md_last_error", "md_destroy",
             "md_log_schedule", "md_set_temperature", "md_scale_velocities", "md_van_hove",
             "md_observables_now", "md_clear_samples", "md_workspace_needed", "md_set_workspace",
-            "md_init_static", "md_set_force_kernel")
+            "md_init_static", "md_set_force_kernel", "md_clear_status")
 
 
 class KamdError(RuntimeError):
@@ -102,6 +102,7 @@ def lib():
             "md_autotune": [P, i32, P],
             "md_set_list_params": [P, f64, i32],
             "md_set_force_kernel": [P, i32, i32],
+            "md_clear_status": [P],
             "md_stats": [P, P],
             "md_get_state": [P, P, C.POINTER(C.c_size_t)],
             "md_set_state": [P, P, C.c_size_t],
@@ -359,6 +360,10 @@ def md_status(ctx):
     return w.value
 
 
+def md_clear_status(ctx):
+    _check(lib().md_clear_status(ctx), ctx)
+
+
 def md_destroy(ctx):
     _check(lib().md_destroy(ctx))
 
@@ -527,6 +532,9 @@ class System:
 
     def status(self):
         return md_status(self.ctx)
+
+    def clear_status(self):
+        md_clear_status(self.ctx)
 
     def sync(self):
         md_sync(self.ctx)

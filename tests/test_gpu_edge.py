@@ -169,4 +169,10 @@ def test_runaway_pair_sets_its_bit(prec):
         s.step_nve(1)
         w = s.status()
         assert w == (md.DEV_RUNAWAY if expect else 0), (r, w)
+        # the pair has flown apart (beyond the cutoff): stopped, and with the
+        # word cleared, later steps are ordinary
+        s.scale_velocities([0.0])
+        s.clear_status()
+        s.step_nve(5)
+        assert s.status() == 0
         s.close()
