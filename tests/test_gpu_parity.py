@@ -169,6 +169,36 @@ def test_nve_fp64_trajectory_matches_oracle():
     s.close()
 
 
+def test_one_fp64_step_matches_oracle_to_1e13():
+    """One velocity-Verlet step (Sec. II.D, in the order of Sec. III.E) in
+    FP64 against the oracle's: positions, velocities and the new
+    accelerations to 1e-13 relative (normwise; the force sums run in another
+    order), image counters equal."""
+    n, T = 2000, 1.0
+    log("case one fp64 step")
+    s = system([(n, T, 12, 1.2)], "fp64")
+    x, y, z, vx, vy, vz, na, L = relaxed(n, T, 12)
+    st = O.State(x, y, z, vx, vy, vz, na, L)
+    st.compute_forces()
+    O.run(st, 0.005, 1)
+    s.step_nve(1)
+    a = s.numpy()
+    img = s.images()
+    assert np.array_equal(img, st.img)
+
+    def rel(keys, ref):
+        num = sum(np.sum((a[k] - r) ** 2) for k, r in zip(keys, ref))
+        return math.sqrt(num / sum(np.sum(r ** 2) for r in ref))
+
+    ex = rel(("x", "y", "z"), (st.x, st.y, st.z))
+    ev = rel(("vx", "vy", "vz"), (st.vx, st.vy, st.vz))
+    ea = rel(("ax", "ay", "az"), (st.ax, st.ay, st.az))
+    log(f"  positions {ex:.2e}, velocities {ev:.2e}, accelerations {ea:.2e}")
+    assert ex <= 1e-13 and ev <= 1e-13 and ea <= 1e-13
+    assert s.status() == 0
+    s.close()
+
+
 @pytest.mark.parametrize("n,dr_mode", [(1000, "paper"), (4000, "halfbox200"), (3000, "short"), (6000, "pruned")])
 def test_rdf_counts_bit_exact(n, dr_mode):
     """Histogram counts equal the oracle's O(N^2) ones.  "pruned": r_max = 4.0
