@@ -252,6 +252,22 @@ def roofline(prof, stats, n, precision):
                          "traffic_over_algorithmic": (traffic / alg_bytes) if traffic else None}}
 
 
+def rdf_first_peaks(s, rep, hist=None):
+    """g_AA, g_AB, g_BB (Eqs. (gAA), (gAB)) of one on-device RDF sample (r_max
+    5.0, 200 bins), host-normalised: (r, g) of each first peak, so that runs
+    in different precisions can be set side by side."""
+    from paper_2001_07089_amd import analysis
+    dr = 5.0 / 200
+    h = s._host(s.rdf(dr, 200) if hist is None else hist)[0]
+    r, g = analysis.rdf(h, rep.n, rep.n_a, rep.box, dr)
+    m = r < 1.5
+    out = {}
+    for k, name in enumerate(("AA", "AB", "BB")):
+        i = int(np.argmax(g[k][m]))
+        out[name] = [float(r[m][i]), float(g[k][m][i])]
+    return out
+
+
 def time_analysis(s, rep):
     """On-device RDF (r_max 5.0, 200 bins) and MSD (one origin, one
     measurement) of the large system, each timed on its own."""
@@ -265,6 +281,7 @@ def time_analysis(s, rep):
     s.stream.synchronize()
     t_rdf = time.perf_counter() - t0
     counts = s._host(h).astype(np.int64)[0].sum(axis=1)
+    peaks = rdf_first_peaks(s, rep, h)
     # the LAMMPS compute rdf layout: 25 bins to the force cutoff 2.5, with
     # coordination numbers (host normalisation of the device counts)
     s.rdf(2.5 / 25, 25)
@@ -281,7 +298,7 @@ def time_analysis(s, rep):
     t_msd = time.perf_counter() - t0
     torch.cuda.synchronize()
     return {"rdf_ms": t_rdf * 1e3, "rdf_r_max": 5.0, "rdf_bins": 200,
-            "rdf_pair_counts_AA_AB_BB": [int(c) for c in counts],
+            "rdf_pair_counts_AA_AB_BB": [int(c) for c in counts], "rdf_first_peaks_r_g": peaks,
             "lammps_rdf_ms": t_lmp * 1e3, "lammps_rdf_coordination_at_2.5_AA_BB_AB":
                 [float(table[-1, 3]), float(table[-1, 5]), float(table[-1, 7])],
             "msd_ms": t_msd * 1e3, "msd_after_100_steps_A_B": [float(m[0, 0]), float(m[0, 1])]}
@@ -297,9 +314,11 @@ def fp64_leg(md, torch, wl, init, equil, warmup, skin, cell_div, steps, profile_
     s.set_list_params(skin, cell_div)
     s.step_nve(warmup)
     el, rows = drift_run(s, torch, steps)
+    peaks = rdf_first_peaks(s, rep)
     prof = md.md_profile(s.ctx, min(100, profile_steps))
     out = {"value": rep.n * steps / el, "unit": "atom-steps/s", "steps": steps, "ms_per_step": el * 1e3 / steps,
-           "drift": drift_stats(rows[0], rep.n), "force_ms": prof["force_ms"], "device_error_word": s.status()}
+           "drift": drift_stats(rows[0], rep.n), "rdf_first_peaks_r_g": peaks, "force_ms": prof["force_ms"],
+           "device_error_word": s.status()}
     s.close()
     return out
 

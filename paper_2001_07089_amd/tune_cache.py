@@ -28,21 +28,26 @@ def default_path() -> str:
     return os.path.join(os.path.expanduser("~"), ".cache", "kamd", "autotune.json")
 
 
-def workload_key(device: str, precision: int, reps) -> str:
+def workload_key(device: str, precision: int, reps, dim: int = 3) -> str:
     """Cache key of a replica set (ctypes Replica array or objects with n, box,
-    temperature attributes)."""
+    temperature attributes).  The density is N / L^dim; planar systems (dim 2)
+    carry a "d2" part, so that they never share a key with a 3-D one."""
     reps = list(reps)
+    dim = 2 if int(dim) == 2 else 3
     n_total = sum(int(r.n) for r in reps)
-    rho = sum(r.n / r.box ** 3 for r in reps) / len(reps)
+    rho = sum(r.n / r.box ** dim for r in reps) / len(reps)
     temp = sum(r.temperature for r in reps) / len(reps)
-    return "|".join([
+    parts = [
         device,
         PRECISION_NAMES.get(int(precision), str(precision)),
         f"n2^{int(math.floor(math.log2(max(n_total, 1))))}",
         f"r2^{int(math.floor(math.log2(len(reps))))}",
         f"rho{round(rho / 0.05) * 0.05:.2f}",
         f"T{round(temp / 0.25) * 0.25:.2f}",
-    ])
+    ]
+    if dim == 2:
+        parts.append("d2")
+    return "|".join(parts)
 
 
 def load(path: str) -> dict:
@@ -85,7 +90,7 @@ def tune(system, probe_steps: int = 100, path: str = None, device: str = None, r
     "cached", "key"} (windows and wg_size None for an entry without them)."""
     path = path or default_path()
     device = device or device_name(getattr(system, "torch", None))
-    key = workload_key(device, system.cfg.precision, system.reps)
+    key = workload_key(device, system.cfg.precision, system.reps, system.cfg.dim)
     hit = None if refresh else load(path).get(key)
     if hit and "skin" in hit and "cell_div" in hit:
         system.set_list_params(float(hit["skin"]), int(hit["cell_div"]))

@@ -74,6 +74,13 @@ def test_key_separates_device_precision_and_workload():
     # a different seed (same class) maps to the same key
     assert k == tune_cache.workload_key("dev", md.PREC_MIXED_FIXED,
                                         md.make_replicas([(r.n, r.n_a, r.box, r.temperature, r.seed + 7)]))
+    # a planar system: its own key, with the density N / L^2
+    p = W.ka_planar(1 << 20, 0.4).replicas[0]
+    flat = md.make_replicas([(p.n, p.n_a, p.box, p.temperature, p.seed)])
+    kp = tune_cache.workload_key("dev", md.PREC_MIXED_FIXED, flat, dim=2)
+    assert kp.endswith("|d2") and "rho1.20" in kp
+    assert kp != tune_cache.workload_key("dev", md.PREC_MIXED_FIXED, flat)
+    assert "d2" not in k
 
 
 def test_corrupt_cache_is_a_miss(tmp_path, fakes):
@@ -101,6 +108,6 @@ def test_shipped_picks_are_well_formed():
     data = tune_cache.load(os.path.join(os.path.dirname(md.__file__), "tuned", "autotune.json"))
     assert data
     for key, e in data.items():
-        assert key.count("|") == 5
+        assert key.count("|") == 5 or (key.count("|") == 6 and key.endswith("|d2"))
         assert 0.2 <= e["skin"] <= 0.5 and e["cell_div"] in (1, 2)
         assert e["windows"] in (0, 1) and e["wg_size"] in (64, 128, 256)
