@@ -64,6 +64,35 @@ __device__ inline int fix_cell(uint32_t u, int nc) { return (int)__umulhi(u, (ui
 
 __device__ inline void set_err(uint32_t *err, uint32_t bit) { atomicOr(err, bit); }
 
+// Streaming accesses: data that a step reads or writes once (the particle's
+// own state, the 32-bit list parts), loaded and stored non-temporally so that
+// it does not displace the neighbour positions the gathers of the force
+// kernels keep reusing from the caches.  (Measured at N = 2^20: the fused
+// step kernel 0.227 -> 0.209 ms.  The 16-bit list parts are not marked: each
+// of their words is read twice, by consecutive passes.)
+template <typename T>
+__device__ inline T ld_stream(const T *p)
+{
+    return __builtin_nontemporal_load(p);
+}
+template <typename T>
+__device__ inline void st_stream(T v, T *p)
+{
+    __builtin_nontemporal_store(v, p);
+}
+__device__ inline uint4 ld_stream(const uint4 *p)
+{
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ inline int4 ld_stream(const int4 *p)
+{
+    typedef int v4i __attribute__((ext_vector_type(4)));
+    const v4i v = __builtin_nontemporal_load(reinterpret_cast<const v4i *>(p));
+    return make_int4(v.x, v.y, v.z, v.w);
+}
+
 // Rebuild decision of replica r for the running step.  Every kernel of the
 // rebuild chain evaluates it identically: nothing it reads changes before the
 // force kernel of the same step closes the check.
@@ -94,9 +123,9 @@ __device__ inline void drift_core(const Dev &d, int s, const RepInfo &R, double 
 {
     const int np = d.npad_total;
     const double L = R.L, invL = R.invL;
-    double r[3] = {d.x[s], d.y[s], d.z[s]};
+    double r[3] = {ld_stream(&d.x[s]), ld_stream(&d.y[s]), ld_stream(&d.z[s])};
     double vn[3];
-    int32_t im[3] = {d.img[s], d.img[np + s], d.img[2 * np + s]};
+    int32_t im[3] = {ld_stream(&d.img[s]), ld_stream(&d.img[np + s]), ld_stream(&d.img[2 * np + s])};
     uint32_t q[3];
     bool fin = true;
     double step2 = 0.0;  // squared length of this step's move (runaway check)
@@ -111,11 +140,11 @@ __device__ inline void drift_core(const Dev &d, int s, const RepInfo &R, double 
         r[k] = wrap_img(r[k], L, invL, im[k]);
         q[k] = to_fix(r[k], invL);
     }
-    d.x[s] = r[0]; d.y[s] = r[1]; d.z[s] = r[2];
-    d.vx[s] = vn[0]; d.vy[s] = vn[1]; d.vz[s] = vn[2];
-    d.img[s] = im[0]; d.img[np + s] = im[1]; d.img[2 * np + s] = im[2];
-    mirror_out[s] = make_uint4(q[0], q[1], q[2], 0u);
-    const uint4 b = d.mbuild[s];
+    st_stream(r[0], &d.x[s]); st_stream(r[1], &d.y[s]); st_stream(r[2], &d.z[s]);
+    st_stream(vn[0], &d.vx[s]); st_stream(vn[1], &d.vy[s]); st_stream(vn[2], &d.vz[s]);
+    st_stream(im[0], &d.img[s]); st_stream(im[1], &d.img[np + s]); st_stream(im[2], &d.img[2 * np + s]);
+    mirror_out[s] = make_uint4(q[0], q[1], q[2], 0u);  // gathered by the next step: cached
+    const uint4 b = ld_stream(&d.mbuild[s]);
     const float ex = (float)(int)(q[0] - b.x), ey = (float)(int)(q[1] - b.y),
                 ez = (float)(int)(q[2] - b.z);
     const float h = (float)(R.L * 2.3283064365386963e-10);

@@ -62,7 +62,7 @@ __device__ inline double rcp_f64(double a)
 // both formats gather four neighbours per pass.
 __device__ inline void list_quad32(const int4 *nb, int k, int jj[4])
 {
-    const int4 q = nb[(k >> 2) * WAVE];
+    const int4 q = ld_stream(nb + (k >> 2) * WAVE);  // read once per step
     jj[0] = q.x;
     jj[1] = q.y;
     jj[2] = q.z;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(WAVE * WPB) void k_force_fp64(Dev d, Model m, int s
     } else if ((s - S.slot0) < S.n) {
         const double h = 0.5 * dt;
         const double a[3] = {fx, fy, fz};
-        const double v[3] = {fma(h, fx, d.vx[s]), fma(h, fy, d.vy[s]), fma(h, fz, d.vz[s])};
+        const double v[3] = {fma(h, fx, ld_stream(&d.vx[s])), fma(h, fy, ld_stream(&d.vy[s])), fma(h, fz, ld_stream(&d.vz[s]))};
         if (ENERGY) ke2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         drift_core(d, s, R, dt, 0.0, 0.0, h, v, a, mirror_out, d2);
         pos4_out[s] = make_double4(d.x[s], d.y[s], d.z[s], 0.0);
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(WAVE * WPB) __attribute__((amdgpu_waves_per_eu(STAG
     } else if ((s - S.slot0) < S.n) {
         const double h = 0.5 * dt;
         const double a[3] = {fx, fy, fz};
-        const double v[3] = {fma(h, fx, d.vx[s]), fma(h, fy, d.vy[s]), fma(h, fz, d.vz[s])};
+        const double v[3] = {fma(h, fx, ld_stream(&d.vx[s])), fma(h, fy, ld_stream(&d.vy[s])), fma(h, fz, ld_stream(&d.vz[s]))};
         if (ENERGY) ke2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         drift_core(d, s, R, dt, 0.0, 0.0, h, v, a, mirror_out, d2);
     }
