@@ -291,23 +291,34 @@ __global__ __launch_bounds__(BLOCK) void k_rb_scatter(Dev d)
     }
 }
 
+// Non-temporal 16-byte store (the build mirror, read once per step).
+__device__ inline void st_stream(uint4 v, uint4 *p)
+{
+    typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+    v4u w = {v.x, v.y, v.z, v.w};
+    __builtin_nontemporal_store(w, reinterpret_cast<v4u *>(p));
+}
+
+// One particle's state from slot v to sorted slot t.  Everything but the
+// mirror is read once here and once more by the list builder's copy back:
+// non-temporal both ways.  The mirror is the list builder's candidates.
 __device__ inline void gather_one(const Dev &d, int v, int t)
 {
     const int np = d.npad_total;
-    d.sx[t] = d.x[v];
-    d.sy[t] = d.y[v];
-    d.sz[t] = d.z[v];
-    d.svx[t] = d.vx[v];
-    d.svy[t] = d.vy[v];
-    d.svz[t] = d.vz[v];
-    d.sax[t] = d.ax[v];
-    d.say[t] = d.ay[v];
-    d.saz[t] = d.az[v];
-    d.simg[t] = d.img[v];
-    d.simg[np + t] = d.img[np + v];
-    d.simg[2 * np + t] = d.img[2 * np + v];
-    d.sid[t] = d.id[v];
-    d.smirror[t] = d.mirror[v];
+    st_stream(ld_stream(&d.x[v]), &d.sx[t]);
+    st_stream(ld_stream(&d.y[v]), &d.sy[t]);
+    st_stream(ld_stream(&d.z[v]), &d.sz[t]);
+    st_stream(ld_stream(&d.vx[v]), &d.svx[t]);
+    st_stream(ld_stream(&d.vy[v]), &d.svy[t]);
+    st_stream(ld_stream(&d.vz[v]), &d.svz[t]);
+    st_stream(ld_stream(&d.ax[v]), &d.sax[t]);
+    st_stream(ld_stream(&d.ay[v]), &d.say[t]);
+    st_stream(ld_stream(&d.az[v]), &d.saz[t]);
+    st_stream(ld_stream(&d.img[v]), &d.simg[t]);
+    st_stream(ld_stream(&d.img[np + v]), &d.simg[np + t]);
+    st_stream(ld_stream(&d.img[2 * np + v]), &d.simg[2 * np + t]);
+    st_stream(ld_stream(&d.id[v]), &d.sid[t]);
+    d.smirror[t] = d.mirror[v];  // the list builder's candidates: cached
 }
 
 // One thread per particle of the replicas that rebuild.  The scatter put the
@@ -382,15 +393,18 @@ __device__ inline int wave_max_all(int v)
 // Two signed 16-bit lanes of one 32-bit register.
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
-// Squared separation in units of 2^16 fixed-point steps, from coordinates
-// reduced to their high 16 bits: x and y packed in one word (x low), z in the
-// low half of another.  Differences wrap modulo 2^16, which is the minimum
-// image, as for the full 32-bit coordinates; sums saturate.
-__device__ inline int r2_coarse(uint32_t ixy, uint32_t iz, uint32_t jxy, uint32_t jz)
+// Squared separation minus `bound` (bound >= 1), in units of 2^16 fixed-point
+// steps, from coordinates reduced to their high 16 bits: x and y packed in
+// one word (x low), z in the low half of another.  Differences wrap modulo
+// 2^16, which is the minimum image, as for the full 32-bit coordinates.  The
+// x-y sum minus the bound lies in [-bound, 2^31 - bound], so only the final
+// sum can saturate, and it does so upwards: the result is negative exactly
+// when the squared separation is below the bound.
+__device__ inline int r2_coarse_below(uint32_t ixy, uint32_t iz, uint32_t jxy, uint32_t jz, int bound)
 {
     const short2_t dxy = __builtin_bit_cast(short2_t, ixy) - __builtin_bit_cast(short2_t, jxy);
     const short2_t dz = __builtin_bit_cast(short2_t, iz) - __builtin_bit_cast(short2_t, jz);
-    return __builtin_amdgcn_sdot2(dz, dz, __builtin_amdgcn_sdot2(dxy, dxy, 0, true), true);
+    return __builtin_amdgcn_sdot2(dz, dz, __builtin_amdgcn_sdot2(dxy, dxy, -bound, true), true);
 }
 
 __device__ inline double gap(int o, int c, double cw, double u)
@@ -439,22 +453,22 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     const int np = d.npad_total;
     uint4 mi = make_uint4(0, 0, 0, 0);
     if (real) {
-        d.x[s] = d.sx[s];
-        d.y[s] = d.sy[s];
-        d.z[s] = d.sz[s];
-        d.vx[s] = d.svx[s];
-        d.vy[s] = d.svy[s];
-        d.vz[s] = d.svz[s];
-        d.ax[s] = d.sax[s];
-        d.ay[s] = d.say[s];
-        d.az[s] = d.saz[s];
-        d.img[s] = d.simg[s];
-        d.img[np + s] = d.simg[np + s];
-        d.img[2 * np + s] = d.simg[2 * np + s];
-        d.id[s] = d.sid[s];
+        st_stream(ld_stream(&d.sx[s]), &d.x[s]);
+        st_stream(ld_stream(&d.sy[s]), &d.y[s]);
+        st_stream(ld_stream(&d.sz[s]), &d.z[s]);
+        st_stream(ld_stream(&d.svx[s]), &d.vx[s]);
+        st_stream(ld_stream(&d.svy[s]), &d.vy[s]);
+        st_stream(ld_stream(&d.svz[s]), &d.vz[s]);
+        st_stream(ld_stream(&d.sax[s]), &d.ax[s]);
+        st_stream(ld_stream(&d.say[s]), &d.ay[s]);
+        st_stream(ld_stream(&d.saz[s]), &d.az[s]);
+        st_stream(ld_stream(&d.simg[s]), &d.img[s]);
+        st_stream(ld_stream(&d.simg[np + s]), &d.img[np + s]);
+        st_stream(ld_stream(&d.simg[2 * np + s]), &d.img[2 * np + s]);
+        st_stream(ld_stream(&d.sid[s]), &d.id[s]);
         mi = d.smirror[s];
-        d.mirror[s] = mi;
-        d.mbuild[s] = mi;
+        d.mirror[s] = mi;  // gathered by the next step: cached
+        st_stream(mi, &d.mbuild[s]);
     }
     if (d.pos4) d.pos4[s] = make_double4(d.x[s], d.y[s], d.z[s], 0.0);  // FP64: gathers see the new order
     const int nc = R.nc;
@@ -660,7 +674,8 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
             cnt += acc;
         };
         auto test_coarse = [&](int j, bool in, uint32_t jxy, uint32_t jz) __attribute__((always_inline)) {
-            const int acc = (int)in & (int)(r2_coarse(ixy, iz, jxy, jz) < r2c);
+            // the sign bit of r2 - r2c
+            const int acc = (int)in & (int)((uint32_t)r2_coarse_below(ixy, iz, jxy, jz, r2c) >> 31);
             buf[cnt & (LIST_STAGE - 1)][lane] = j + dl;
             cnt += acc;
         };
