@@ -440,7 +440,7 @@ template <bool STAGE>
 __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
 {
     __shared__ int32_t stage[WAVES_PER_BLOCK][LIST_STAGE][WAVE];
-    __shared__ uint32_t win_s[WAVES_PER_BLOCK][3][LIST_WIN + LIST_UNROLL];
+    __shared__ __attribute__((aligned(16))) uint32_t win_s[WAVES_PER_BLOCK][3][LIST_WIN + LIST_UNROLL];
     if (d.rb_any[0] == 0) return;
     const int w = rb_work_wave(d);  // each XCD walks a contiguous part of the worklist
     if (w < 0) return;
@@ -495,6 +495,7 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     uint32_t *wx = win_s[threadIdx.x / WAVE][0];
     uint32_t *wy = win_s[threadIdx.x / WAVE][1];
     uint32_t *wz = win_s[threadIdx.x / WAVE][2];
+    uint2 *wc = reinterpret_cast<uint2 *>(wx);  // the coarse window: spans wx and wy
     const int rows = d.rows;
     int row = 0;  // 32-bit words of the list used so far
     int total = 0;
@@ -719,9 +720,8 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                 for (int t = 0; t < 3; ++t) {
                     const int e = e0 + t * WAVE + lane;
                     if (e < n) {
-                        if (coarse) {
-                            wx[e] = (m[t].x >> 16) | (m[t].y & 0xffff0000u);
-                            wy[e] = m[t].z >> 16;
+                        if (coarse) {  // (x-y word, z word) pairs: one 8-byte read per candidate
+                            wc[e] = make_uint2((m[t].x >> 16) | (m[t].y & 0xffff0000u), m[t].z >> 16);
                         } else {
                             wx[e] = m[t].x;
                             wy[e] = m[t].y;
@@ -741,13 +741,13 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
                 for (; j + LIST_UNROLL <= en; j += LIST_UNROLL) {  // whole batches
                     const int o = j - lo;
 #pragma unroll
-                    for (int u = 0; u < LIST_UNROLL; ++u) test_coarse(j + u, true, wx[o + u], wy[o + u]);
+                    for (int u = 0; u < LIST_UNROLL; ++u) test_coarse(j + u, true, wc[o + u].x, wc[o + u].y);
                     if (__any(cnt - done > LIST_STAGE - LIST_UNROLL)) flush();
                 }
                 if (j < en) {  // the last, partial batch
                     const int o = j - lo;
 #pragma unroll
-                    for (int u = 0; u < LIST_UNROLL; ++u) test_coarse(j + u, j + u < en, wx[o + u], wy[o + u]);
+                    for (int u = 0; u < LIST_UNROLL; ++u) test_coarse(j + u, j + u < en, wc[o + u].x, wc[o + u].y);
                 }
             } else {
                 for (; j + LIST_UNROLL <= en; j += LIST_UNROLL) {  // whole batches
