@@ -91,6 +91,8 @@ def parse():
     p.add_argument("--no-batch-large", action="store_true", help="skip the 64-replica large batch")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--only-headline", action="store_true", help="the headline and its drift only")
+    p.add_argument("--only-batch", action="store_true",
+                   help="the 256-replica leg only (its JSON object on one line), e.g. for a kernel trace of it")
     p.add_argument("--cpu-steps", type=int, default=3, help="oracle steps per all-core run")
     p.add_argument("--batch-drift-study", action="store_true",
                    help="also run the 256-replica batch's worst-drifting replicas in FP64 at dt 0.005 and 0.0025")
@@ -643,6 +645,13 @@ def main():
 
     if a.calibrate_copy:
         calibrate_copy(torch, a.calibrate_copy)
+        return
+
+    if a.only_batch:
+        t1 = time.perf_counter()
+        out = batched(md, torch, W, a.drift_steps)
+        log(f"batched ({time.perf_counter() - t1:.1f} s): {out}")
+        print(json.dumps(out), flush=True)
         return
 
     wl = {"small": W.ka_small, "medium": W.ka_medium, "large": W.ka_large}[a.workload]()
