@@ -49,7 +49,7 @@ constexpr int GATE_THREADS = 1024;
 // thread, numbered from first), the numbers first .. first + n - 1 to out,
 // in thread order.  Returns the number appended.  Every thread of the block
 // calls it.  The threads with n > 0 are compacted first; then the whole block
-// writes their ranges one after the other with plain stores.
+// writes their ranges with plain stores.
 struct GateShared {
     int wtot[GATE_THREADS / WAVE];  // per wavefront: sum of n, then its exclusive prefix
     int wcnt[GATE_THREADS / WAVE];  // per wavefront: threads with n > 0, then their prefix
@@ -93,9 +93,19 @@ __device__ inline int gate_append(int32_t *out, int n, int first, GateShared &g)
         g.n[k] = n;
     }
     __syncthreads();
+    // The block spreads the output positions, not the ranges: position o
+    // belongs to the last range whose start is <= o (the starts ascend, and
+    // the first is 0), found by a binary search.
     const int cnt = g.cnt, tot = g.tot;
-    for (int k = 0; k < cnt; ++k)
-        for (int i = t; i < g.n[k]; i += GATE_THREADS) out[g.at[k] + i] = g.first[k] + i;
+    for (int o = t; o < tot; o += GATE_THREADS) {
+        int lo = 0, hi = cnt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (g.at[mid] <= o) lo = mid;
+            else hi = mid - 1;
+        }
+        out[o] = g.first[lo] + (o - g.at[lo]);
+    }
     __syncthreads();  // the shared arrays are reused
     return tot;
 }
