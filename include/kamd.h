@@ -370,7 +370,13 @@ int md_graph_launch(kamd_ctx *ctx);
  * hold every candidate (md_workspace_needed then gives the size).  Syncs. */
 int md_autotune(kamd_ctx *ctx, int32_t probe_steps, double *host_out);
 
-/* Change skin and cell division (forces a rebuild at the next step). */
+/* Change skin and cell division (forces a rebuild at the next step).  With
+ * cell_div 1 a replica may build its lists with a smaller skin, down to two
+ * thirds of the given one, where that gives its box enough more cells per
+ * edge to cut the cell volume by 1.3x or more (small boxes, whose cells are
+ * otherwise well over a list radius wide); the largest such skin is taken,
+ * and the replica's rebuild test uses it too.  md_stats reports the smallest
+ * skin in use.  The forces do not depend on the skin. */
 int md_set_list_params(kamd_ctx *ctx, double skin, int32_t cell_div);
 
 /* Step-kernel variant.  windows (mixed precisions): 1 gathers
@@ -384,10 +390,11 @@ int md_set_list_params(kamd_ctx *ctx, double skin, int32_t cell_div);
  * for windows = 1 in FP64.  Syncs. */
 int md_set_force_kernel(kamd_ctx *ctx, int32_t windows, int32_t wg_size);
 
-/* Statistics: host_out (host, FP64 [13]) = {steps, rebuilds, n_total,
+/* Statistics: host_out (host, FP64 [14]) = {steps, rebuilds, n_total,
  * list_rows, mean_list_len, max_list_len, skin, cell_div, mean_list_bytes,
  * windows (the force-kernel variant), fraction of list parts gathered from a
- * window, step-kernel threads per block, mean_walked}.  List lengths count
+ * window, step-kernel threads per block, mean_walked, skin_min (the smallest
+ * skin a replica uses; see md_set_list_params)}.  List lengths count
  * partners at the last build (without wavefront padding); mean_list_bytes is
  * their stored size per particle (4 bytes per 32-bit entry, 2 per 16-bit
  * entry); mean_walked is the number of entries the force kernels walk per

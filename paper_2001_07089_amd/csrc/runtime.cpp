@@ -197,6 +197,16 @@ constexpr int64_t MAX_SEG_CELLS = (int64_t)1 << 24;
 constexpr int64_t MAX_PLAN_CELLS = (int64_t)1 << 26;
 
 static int cell_cap(int dim) { return dim == 2 ? 4096 : 256; }  // nc^(dim) <= MAX_SEG_CELLS
+// Skin per replica.  With one cell per list radius a box of edge L has
+// floor(L / list radius) cells per edge, so in small boxes a cell can be up
+// to twice the list radius wide, and every particle tests the particles of 9
+// stencil rows of such cells.  Where a skin of no less than SKIN_TRIM times
+// the requested one buys enough cells per edge to cut the cell volume by at
+// least CELL_GAIN, the replica takes the largest skin that gets them: it
+// rebuilds somewhat more often and tests far fewer candidates per build.
+// The pair set within the cutoff, and so every force, does not depend on it.
+constexpr double SKIN_TRIM = 2.0 / 3.0;
+constexpr double CELL_GAIN = 1.3;
 
 static double list_skin(const kamd_config *cfg) { return cfg->skin < 0.0 ? 0.3 : cfg->skin; }
 
@@ -214,16 +224,26 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
     double rcmax;
     model_from(cfg->model, m, rcmax);
     const int reach = cell_div <= 0 ? 1 : cell_div;
-    const double rlist = rcmax + skin;
     const double cap = cfg->list_capacity > 0.0 ? cfg->list_capacity : 1.6;
     P = Plan();
     P.fp64 = cfg->precision == KAMD_PREC_FP64;
     const bool planar = dim_of(cfg) == 2;
-    auto cells_per_edge = [&](double box) {
-        return (int)std::max(1.0, std::min(std::floor(box * reach / rlist), (double)cell_cap(dim_of(cfg))));
+    auto cells_per_edge = [&](double box, double s) {
+        return (int)std::max(1.0, std::min(std::floor(box * reach / (rcmax + s)), (double)cell_cap(dim_of(cfg))));
     };
+    auto rep_skin = [&](double box) {
+        if (reach != 1 || !(skin > 0.0)) return skin;
+        const double lo = SKIN_TRIM * skin;
+        const int n0 = cells_per_edge(box, skin), n1 = cells_per_edge(box, lo);
+        if (n1 < 3 || std::pow((double)n1 / n0, planar ? 2 : 3) < CELL_GAIN) return skin;
+        double s = std::min(skin, box / n1 - rcmax);  // the largest skin with n1 cells, up to rounding
+        while (s > lo && cells_per_edge(box, s) < n1) s = std::nextafter(s, 0.0);
+        return std::max(s, lo);
+    };
+    std::vector<double> rskin(n_rep);
     for (int r = 0; r < n_rep; ++r) {  // the grid size first (an oversize plan is refused)
-        const int64_t nc = cells_per_edge(reps[r].box);
+        rskin[r] = rep_skin(reps[r].box);
+        const int64_t nc = cells_per_edge(reps[r].box, rskin[r]);
         P.ncells_wide += 2 * (planar ? nc * nc : nc * nc * nc);
     }
     const bool fits = P.ncells_wide <= MAX_PLAN_CELLS;
@@ -240,19 +260,20 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
         R.caller_off = K.offset;
         R.n = K.n;
         R.na = K.n_a;
-        R.skin = skin;
-        const double half = 0.5 * skin;
+        const double skin_r = rskin[r];
+        R.skin = skin_r;
+        const double half = 0.5 * skin_r;
         R.disp_thr2 = half * half * (1.0 - 1e-5);
         // a move of half the smallest sigma in one step (a normal step moves
         // about a hundredth of that) marks an unstable, runaway integration
         const double smin = std::min(cfg->model.sigma[0], std::min(cfg->model.sigma[1], cfg->model.sigma[2]));
         R.run2 = 0.25 * smin * smin;
-        const int nc = cells_per_edge(K.box);
+        const int nc = cells_per_edge(K.box, skin_r);
         R.nc = nc;
         const double h = K.box / 4294967296.0;
         for (int p = 0; p < 3; ++p) {
             const double rc = cfg->model.rc_factor * cfg->model.sigma[p];
-            const double rl = rc + skin;
+            const double rl = rc + skin_r;
             R.rc2_fx[p] = (float)((rc / h) * (rc / h));
             R.rl2_fx[p] = (float)((rl / h) * (rl / h) * (1.0 + 4e-6));
             R.sig2_fx[p] = (float)((cfg->model.sigma[p] / h) * (cfg->model.sigma[p] / h));
@@ -291,7 +312,7 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
         const double rhoA = K.n_a / V, rhoB = (K.n - K.n_a) / V;
         const double pi43 = 4.0 / 3.0 * M_PI;
         auto vol = [&](int p) {
-            double rl = cfg->model.rc_factor * cfg->model.sigma[p] + skin;
+            double rl = cfg->model.rc_factor * cfg->model.sigma[p] + skin_r;
             return planar ? M_PI * rl * rl : pi43 * rl * rl * rl;
         };
         const double rowsA = std::max(K.n_a > 0 ? rhoA * vol(0) + rhoB * vol(1) : 0.0,
@@ -1506,6 +1527,9 @@ extern "C" int md_stats(kamd_ctx *c, double *host_out)
     host_out[10] = lb.empty() ? 0.0 : (double)parts_staged / (2.0 * lb.size());
     host_out[11] = (double)(WAVE * c->force_wpb);
     host_out[12] = cntr ? walked / cntr : 0.0;
+    double smin = c->skin;
+    for (const RepInfo &R : c->plan.rinfo) smin = std::min(smin, R.skin);
+    host_out[13] = smin;
     return KAMD_OK;
 }
 

@@ -326,10 +326,10 @@ def md_set_force_kernel(ctx, windows: int, wg_size: int = 0):
 
 
 def md_stats(ctx):
-    out = np.zeros(13)
+    out = np.zeros(14)
     _check(lib().md_stats(ctx, out.ctypes.data), ctx)
     keys = ("steps", "rebuilds", "n_total", "list_rows", "mean_list_len", "max_list_len", "skin", "cell_div",
-            "mean_list_bytes", "windows", "staged_fraction", "wg_size", "mean_walked")
+            "mean_list_bytes", "windows", "staged_fraction", "wg_size", "mean_walked", "skin_min")
     return dict(zip(keys, out.tolist()))
 
 

@@ -795,14 +795,16 @@ def test_list_statistics_count_16bit_entries():
     s.close()
 
 
-@pytest.mark.parametrize("n,rho", [(4000, 1.2), (3000, 0.02), (3000, 2.5e-4)])
+@pytest.mark.parametrize("n,rho", [(4000, 1.2), (3020, 1.2), (3000, 0.02), (3000, 2.5e-4)])
 def test_list_holds_every_pair_within_the_list_radius(n, rho):
     """Every ordered pair closer than its list radius r_c,ab + skin (Sec. III.C)
-    is in the Verlet list, and few others are.  The boxes of 14.9 and 53.1
-    use the list builder's candidate test on coordinates cut to 16 bits; the
-    box of 228.9 uses the full 32-bit test.  Exact pair counts: the oracle's
-    O(N^2) distance histogram with bin edges on the three list radii."""
-    skin, dr = 0.3, 0.1
+    is in the Verlet list, and few others are.  The boxes of 14.9, 13.6 and
+    53.1 use the list builder's candidate test on coordinates cut to 16 bits;
+    the box of 228.9 uses the full 32-bit test.  The box of 13.6 has 4 cells
+    per edge at skin 0.3 and 5 at the skin it builds with (0.22, reported as
+    skin_min).  Exact pair counts: the oracle's O(N^2) distance histogram, one
+    per pair type, with 100 bins up to that type's list radius."""
+    skin = 0.3
     L = W.box_for(n, rho)
     na = W.n_a_for(n)
     log(f"case list superset n={n} rho={rho} L={L:.1f}")
@@ -812,11 +814,17 @@ def test_list_holds_every_pair_within_the_list_radius(n, rho):
     a = s.numpy(("x", "y", "z"))
     st = md.md_stats(s.ctx)
     s.close()
-    h = O.rdf_hist(a["x"], a["y"], a["z"], na, L, dr, 30).astype(np.int64)
+    used = st["skin_min"]
+    if n == 3020:
+        assert 0.2 <= used < 0.25
+    else:
+        assert used == skin
     # hist rows AA, AB, BB: same-type pairs counted twice, AB pairs once
-    rl = [O.KA_RC_FACTOR * sg + skin for sg in O.KA_SIGMA]
-    k = [int(round(r / dr)) for r in rl]
-    exact = int(h[0, :k[0]].sum() + 2 * h[1, :k[1]].sum() + h[2, :k[2]].sum())
+    exact = 0
+    for p, mult in ((0, 1), (1, 2), (2, 1)):
+        rl = O.KA_RC_FACTOR * O.KA_SIGMA[p] + used
+        h = O.rdf_hist(a["x"], a["y"], a["z"], na, L, rl / 100, 100).astype(np.int64)
+        exact += mult * int(h[p].sum())
     listed = int(round(st["mean_list_len"] * n))
-    log(f"  exact {exact} listed {listed}")
+    log(f"  skin {used:.4f}, exact {exact} listed {listed}")
     assert exact <= listed <= exact * 1.004 + 8
