@@ -309,25 +309,25 @@ __device__ inline void st_stream(uint4 v, uint4 *p)
     __builtin_nontemporal_store(w, reinterpret_cast<v4u *>(p));
 }
 
-// One particle's state from slot v to sorted slot t.  Everything but the
-// mirror is read once here and once more by the list builder's copy back:
-// non-temporal both ways.  The mirror is the list builder's candidates.
+// One particle's state from slot v to sorted slot t.  The old copy is dead
+// once read (non-temporal loads); the sorted copy is read back soon by the
+// list builder, and the sorted mirror is its candidates (plain stores).
 __device__ inline void gather_one(const Dev &d, int v, int t)
 {
     const int np = d.npad_total;
-    st_stream(ld_stream(&d.x[v]), &d.sx[t]);
-    st_stream(ld_stream(&d.y[v]), &d.sy[t]);
-    st_stream(ld_stream(&d.z[v]), &d.sz[t]);
-    st_stream(ld_stream(&d.vx[v]), &d.svx[t]);
-    st_stream(ld_stream(&d.vy[v]), &d.svy[t]);
-    st_stream(ld_stream(&d.vz[v]), &d.svz[t]);
-    st_stream(ld_stream(&d.ax[v]), &d.sax[t]);
-    st_stream(ld_stream(&d.ay[v]), &d.say[t]);
-    st_stream(ld_stream(&d.az[v]), &d.saz[t]);
-    st_stream(ld_stream(&d.img[v]), &d.simg[t]);
-    st_stream(ld_stream(&d.img[np + v]), &d.simg[np + t]);
-    st_stream(ld_stream(&d.img[2 * np + v]), &d.simg[2 * np + t]);
-    st_stream(ld_stream(&d.id[v]), &d.sid[t]);
+    d.sx[t] = ld_stream(&d.x[v]);
+    d.sy[t] = ld_stream(&d.y[v]);
+    d.sz[t] = ld_stream(&d.z[v]);
+    d.svx[t] = ld_stream(&d.vx[v]);
+    d.svy[t] = ld_stream(&d.vy[v]);
+    d.svz[t] = ld_stream(&d.vz[v]);
+    d.sax[t] = ld_stream(&d.ax[v]);
+    d.say[t] = ld_stream(&d.ay[v]);
+    d.saz[t] = ld_stream(&d.az[v]);
+    d.simg[t] = ld_stream(&d.img[v]);
+    d.simg[np + t] = ld_stream(&d.img[np + v]);
+    d.simg[2 * np + t] = ld_stream(&d.img[2 * np + v]);
+    d.sid[t] = ld_stream(&d.id[v]);
     d.smirror[t] = d.mirror[v];  // the list builder's candidates: cached
 }
 
