@@ -372,11 +372,11 @@ int md_autotune(kamd_ctx *ctx, int32_t probe_steps, double *host_out);
 
 /* Change skin and cell division (forces a rebuild at the next step).  With
  * cell_div 1 a replica may build its lists with a smaller skin, down to two
- * thirds of the given one, where that gives its box enough more cells per
- * edge to cut the cell volume by 1.3x or more (small boxes, whose cells are
- * otherwise well over a list radius wide); the largest such skin is taken,
- * and the replica's rebuild test uses it too.  md_stats reports the smallest
- * skin in use.  The forces do not depend on the skin. */
+ * thirds of the given one, where that gives its box more cells per edge and
+ * (cell-volume ratio) x (smaller skin / skin) is 1.15 or more: small boxes,
+ * whose cells are otherwise well over a list radius wide.  The largest such
+ * skin is taken, and the replica's rebuild test uses it too.  md_stats
+ * reports the smallest skin in use.  The forces do not depend on the skin. */
 int md_set_list_params(kamd_ctx *ctx, double skin, int32_t cell_div);
 
 /* Step-kernel variant.  windows (mixed precisions): 1 gathers

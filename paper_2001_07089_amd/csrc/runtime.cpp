@@ -200,13 +200,14 @@ static int cell_cap(int dim) { return dim == 2 ? 4096 : 256; }  // nc^(dim) <= M
 // Skin per replica.  With one cell per list radius a box of edge L has
 // floor(L / list radius) cells per edge, so in small boxes a cell can be up
 // to twice the list radius wide, and every particle tests the particles of 9
-// stencil rows of such cells.  Where a skin of no less than SKIN_TRIM times
-// the requested one buys enough cells per edge to cut the cell volume by at
-// least CELL_GAIN, the replica takes the largest skin that gets them: it
-// rebuilds somewhat more often and tests far fewer candidates per build.
-// The pair set within the cutoff, and so every force, does not depend on it.
+// stencil rows of such cells.  A replica takes a smaller skin, no less than
+// SKIN_TRIM times the requested one, where that buys more cells per edge and
+// the list build's work per step falls by CELL_GAIN or more: the candidates
+// per build fall as the cell volume, the builds grow as 1 / skin (the largest
+// skin that gets the extra cells is taken).  The pair set within the
+// cutoff, and so every force, does not depend on it.
 constexpr double SKIN_TRIM = 2.0 / 3.0;
-constexpr double CELL_GAIN = 1.3;
+constexpr double CELL_GAIN = 1.15;
 
 static double list_skin(const kamd_config *cfg) { return cfg->skin < 0.0 ? 0.3 : cfg->skin; }
 
@@ -235,10 +236,11 @@ static void make_plan(const kamd_config *cfg, const kamd_replica *reps, int n_re
         if (reach != 1 || !(skin > 0.0)) return skin;
         const double lo = SKIN_TRIM * skin;
         const int n0 = cells_per_edge(box, skin), n1 = cells_per_edge(box, lo);
-        if (n1 < 3 || std::pow((double)n1 / n0, planar ? 2 : 3) < CELL_GAIN) return skin;
+        if (n1 < 3 || n1 <= n0) return skin;
         double s = std::min(skin, box / n1 - rcmax);  // the largest skin with n1 cells, up to rounding
         while (s > lo && cells_per_edge(box, s) < n1) s = std::nextafter(s, 0.0);
-        return std::max(s, lo);
+        s = std::max(s, lo);
+        return std::pow((double)n1 / n0, planar ? 2 : 3) * (s / skin) >= CELL_GAIN ? s : skin;
     };
     std::vector<double> rskin(n_rep);
     for (int r = 0; r < n_rep; ++r) {  // the grid size first (an oversize plan is refused)
