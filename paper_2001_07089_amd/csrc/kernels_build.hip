@@ -462,10 +462,14 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
     const bool real = (s - S.slot0) < S.n;
     const int np = d.npad_total;
     uint4 mi = make_uint4(0, 0, 0, 0);
+    double px, py, pz;  // the position, for the FP64 packed copy
     if (real) {
-        st_stream(ld_stream(&d.sx[s]), &d.x[s]);
-        st_stream(ld_stream(&d.sy[s]), &d.y[s]);
-        st_stream(ld_stream(&d.sz[s]), &d.z[s]);
+        px = ld_stream(&d.sx[s]);
+        py = ld_stream(&d.sy[s]);
+        pz = ld_stream(&d.sz[s]);
+        st_stream(px, &d.x[s]);
+        st_stream(py, &d.y[s]);
+        st_stream(pz, &d.z[s]);
         st_stream(ld_stream(&d.svx[s]), &d.vx[s]);
         st_stream(ld_stream(&d.svy[s]), &d.vy[s]);
         st_stream(ld_stream(&d.svz[s]), &d.vz[s]);
@@ -479,8 +483,12 @@ __global__ __launch_bounds__(BLOCK) void k_rb_list(Dev d, int reach)
         mi = d.smirror[s];
         d.mirror[s] = mi;  // gathered by the next step: cached
         st_stream(mi, &d.mbuild[s]);
+    } else {
+        px = d.x[s];
+        py = d.y[s];
+        pz = d.z[s];
     }
-    if (d.pos4) d.pos4[s] = make_double4(d.x[s], d.y[s], d.z[s], 0.0);  // FP64: gathers see the new order
+    if (d.pos4) d.pos4[s] = make_double4(px, py, pz, 0.0);  // FP64: gathers see the new order
     const int nc = R.nc;
     const int noff = min(nc, 2 * reach + 1);
     const bool whole = nc < 2 * reach + 1;  // every cell of a row is in the stencil
