@@ -93,14 +93,6 @@ __device__ inline int4 ld_stream(const int4 *p)
     return make_int4(v.x, v.y, v.z, v.w);
 }
 
-// Rebuild decision of replica r for the running step.  Every kernel of the
-// rebuild chain evaluates it identically: nothing it reads changes before the
-// force kernel of the same step closes the check.
-__device__ inline bool rebuild_flag(const Dev &d, int r)
-{
-    return d.rb_force[r] != 0 || (double)__uint_as_float(d.maxdisp[r]) > d.rep[r].disp_thr2;
-}
-
 // ------------------------------------------------ integration helpers
 __device__ inline double wrap_img(double u, double L, double invL, int32_t &img)
 {

@@ -44,6 +44,26 @@ namespace kamd {
 // after one load; on a step where a few replicas of a batch rebuild, the
 // per-wave kernels spread just their work over the whole device.
 constexpr int GATE_THREADS = 1024;
+// Replicas come along with those that must rebuild (rebuild_flag) while the
+// latter have fewer wavefronts than this: four per SIMD of 256 CUs.
+constexpr int LIST_ALONG_WAVES = 4096;
+
+// Rebuild decision of replica r for the running step.  A replica must
+// rebuild when forced or when a particle has moved more than half its skin
+// since the last build.  On a step where the replicas that must rebuild are
+// too few to fill the device (the gate decides, rb_any[1]), the others whose
+// largest move has passed REBUILD_ALONG of that come along (`along`): the
+// rebuilds of a batch's replicas then fall on fewer steps, whose list builds
+// would otherwise each run at the latency of a lone wavefront (an early
+// rebuild is always valid).  Every kernel of the rebuild chain evaluates it
+// identically: nothing it reads changes before the force kernel of the same
+// step closes the check.
+constexpr double REBUILD_ALONG = 0.8;
+__device__ inline bool rebuild_flag(const Dev &d, int r, bool along)
+{
+    const double m2 = (double)__uint_as_float(d.maxdisp[r]), t2 = d.rep[r].disp_thr2;
+    return d.rb_force[r] != 0 || m2 > t2 || (along && m2 > REBUILD_ALONG * REBUILD_ALONG * t2);
+}
 
 // Append, for the replicas of one chunk (one per thread, n of them per
 // thread, numbered from first), the numbers first .. first + n - 1 to out,
@@ -113,20 +133,33 @@ __device__ inline int gate_append(int32_t *out, int n, int first, GateShared &g)
 __global__ __launch_bounds__(GATE_THREADS) void k_rb_gate(Dev d)
 {
     __shared__ GateShared g;
+    __shared__ int wmust;
+    // the wavefronts of the replicas that must rebuild; the others come
+    // along only while those leave most of the device idle
+    if (threadIdx.x == 0) wmust = 0;
+    __syncthreads();
+    for (int r = threadIdx.x; r < d.nrep; r += GATE_THREADS)
+        if (rebuild_flag(d, r, false)) atomicAdd(&wmust, d.rep[r].wave1 - d.rep[r].wave0);
+    __syncthreads();
+    const int wm = wmust;
+    const bool along = wm > 0 && wm < LIST_ALONG_WAVES;
     int nwl = 0;
-    for (int r0 = 0; r0 < d.nrep; r0 += GATE_THREADS) {
+    for (int r0 = 0; wm > 0 && r0 < d.nrep; r0 += GATE_THREADS) {
         const int r = r0 + threadIdx.x;
         int nw = 0, w0 = 0;
         if (r < d.nrep) {
             const RepInfo &R = d.rep[r];
             w0 = R.wave0;
-            if (rebuild_flag(d, r)) nw = R.wave1 - R.wave0;
+            if (rebuild_flag(d, r, along)) nw = R.wave1 - R.wave0;
         }
         // most steps rebuild nothing: skip the compaction (block-uniform)
         if (!__syncthreads_or(nw > 0)) continue;
         nwl += gate_append(d.rb_wlist + nwl, nw, w0, g);
     }
-    if (threadIdx.x == 0) d.rb_any[0] = nwl;
+    if (threadIdx.x == 0) {
+        d.rb_any[0] = nwl;
+        d.rb_any[1] = along ? 1 : 0;
+    }
 }
 
 // Worklist entry of this wavefront for the per-wave kernels that run one
@@ -211,7 +244,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_rb_scan_sum(Dev d)
     const SegInfo &S = d.seg[blockIdx.x];
     const int c = blockIdx.y;
     const int n = chunk_cells(S, c);
-    if (n <= 0 || !rebuild_flag(d, S.rep)) return;
+    if (n <= 0 || !rebuild_flag(d, S.rep, d.rb_any[1] != 0)) return;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const int4 *cnt = reinterpret_cast<const int4 *>(d.cell_count + CELL_SUBX * (S.cell0 + c * SCAN_CHUNK));
     int sum = 0;
@@ -241,7 +274,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_rb_scan(Dev d)
     const SegInfo &S = d.seg[blockIdx.x];
     const int c = blockIdx.y;
     const int n = chunk_cells(S, c);
-    if (n <= 0 || !rebuild_flag(d, S.rep)) return;
+    if (n <= 0 || !rebuild_flag(d, S.rep, d.rb_any[1] != 0)) return;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     if (t == 0) {
         int carry = 0;  // the particles of the segment's chunks before this one

@@ -78,10 +78,12 @@ def test_batch_with_multi_chunk_segments_equals_replicas_alone():
             assert np.array_equal(ref[k][sl], alone[k]), (r, k)
         assert np.array_equal(ref_img[:, sl], img), r
         off += r[0]
-    # every replica rebuilt as often in the batch as alone, and not all as
-    # often as each other: some steps rebuilt some replicas and not others
-    assert st["rebuilds"] == sum(counts)
+    # the replicas do not rebuild equally often alone, so some steps rebuilt
+    # some replicas and not others; in the batch a replica also rebuilds
+    # early, along with one that must, on steps where those that must leave
+    # the device mostly idle (at most 4376 wavefronts here, against 4096)
     assert len(set(counts)) > 1
+    assert sum(counts) <= st["rebuilds"] <= 1.5 * sum(counts)
 
 
 def test_forces_after_partial_rebuilds_match_oracle():
